@@ -1,0 +1,179 @@
+/*
+ * lqmg.h -- C ABI of the MI355X eigensolver for the Hermitian Wilson-Dirac
+ * operator Q = gamma5 D: Rayleigh quotient iteration whose shifted systems
+ * (Q - sigma) are solved by FGMRES preconditioned with gamma5-preserving
+ * aggregation multigrid.  Method: Bali et al., "(Approximate) Low-Mode
+ * Averaging with a new Multigrid Eigensolver" (Lattice 2015), sec. 2, Alg. 1.
+ *
+ * Conventions (all calls):
+ *   - lattice dims[4] = {X, Y, Z, T}; canonical site index
+ *     n = x + X*(y + Y*(z + Z*t)) (x fastest); V = X*Y*Z*T.
+ *   - gauge field U: device array [4][9][V] of complex (mu = x,y,z,t; entry
+ *     3*a + b of U_mu(n), which maps colour b at n + mu_hat to colour a at n).
+ *   - spinor field: device array [12][V] of complex, component 3*s + c
+ *     (spin s, colour c); several fields stack as [n][12][V].
+ *   - gamma basis: chiral, gamma5 = -g1 g2 g3 g4 = diag(1,1,-1,-1) (sec. 2);
+ *     gamma_k = [[0, i sigma_k], [-i sigma_k, 0]], gamma_t = [[0,1],[1,0]].
+ *   - D psi(n) = (4 + m0) psi(n) - 1/2 sum_mu [(1 - gamma_mu) U_mu(n) psi(n+mu)
+ *                + (1 + gamma_mu) U_mu(n-mu)^dag psi(n-mu)], the t hop across
+ *     the boundary multiplied by t_bc (-1 antiperiodic, +1 periodic).
+ *   - device pointers are hipMalloc'd memory (e.g. torch tensors) on the
+ *     device that was current at lq_create; the caller owns them.  The
+ *     library never frees or keeps them past the call, except that mg_setup
+ *     copies U (and the multigrid state derived from it) into context memory.
+ *   - every call returns 0 on success, >0 when it completed with a warning
+ *     (LQ_WARN_NOCONV: an iteration limit was reached; outputs hold the last
+ *     iterate), <0 on error; lq_last_error() then describes it.
+ *   - a context is bound to one stream and is not thread safe.  q_apply and
+ *     q_apply_c64 are asynchronous on that stream; all other calls return
+ *     after the device work they issued has completed.
+ */
+#ifndef LQMG_H
+#define LQMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lq_ctx lq_ctx;
+typedef struct { double re, im; } lq_c128;   /* layout of torch.complex128 */
+typedef struct { float re, im; } lq_c64;     /* layout of torch.complex64  */
+
+enum {
+  LQ_OK = 0,
+  LQ_WARN_NOCONV = 1,
+  LQ_ERR_ARG = -1,     /* invalid argument: dims, sizes, aggregate shapes, NULL */
+  LQ_ERR_STATE = -2,   /* call order: e.g. a solve before mg_setup */
+  LQ_ERR_HIP = -3,     /* a HIP runtime call failed */
+  LQ_ERR_OOM = -4,     /* device allocation failed */
+  LQ_ERR_NUMERIC = -5  /* breakdown: non-finite values or a singular local basis */
+};
+
+enum { LQ_PREC_FP64 = 0, LQ_PREC_MIXED = 1 };   /* multigrid arithmetic */
+enum { LQ_SMOOTH_SAP = 0, LQ_SMOOTH_GMRES = 1 };
+
+/* Multigrid / solver parameters (sec. 2: mu, nu, smoother, coarse GMRES, the
+ * FP64 FGMRES of sec. 2.2, the setup of sec. 2.1).  lq_params_default fills
+ * the defaults; pass NULL to mg_setup to use them. */
+typedef struct {
+  int precision;        /* LQ_PREC_FP64: everything FP64; LQ_PREC_MIXED: the
+                           multigrid preconditioner in FP32 under FP64 FGMRES */
+  int smoother;         /* LQ_SMOOTH_SAP (SAP on D_sigma = gamma5 (Q - sigma)
+                           with rhs gamma5 r) or LQ_SMOOTH_GMRES (GMRES on Q - sigma) */
+  int pre;              /* mu: pre-smoothing steps (SAP sweeps or GMRES calls) */
+  int post;             /* nu: post-smoothing steps */
+  int sap_mr;           /* minimal-residual steps per SAP block solve */
+  int gmres_smooth_m;   /* Krylov steps per GMRES smoother call */
+  int coarse_m;         /* coarse GMRES restart length */
+  int coarse_restarts;  /* coarse GMRES restarts after the first cycle */
+  double coarse_tol;    /* coarse GMRES relative residual target */
+  int fgmres_m;         /* outer FGMRES restart length */
+  int fgmres_restarts;  /* outer FGMRES restarts after the first cycle */
+  int n_init;           /* setup: smoother passes on the random start vectors */
+  int n_setup;          /* setup: multigrid passes over the test vectors */
+  int rqi_block;        /* RQI: shifted systems solved together (1..16) */
+  int rqi_max_sweeps;   /* RQI: maximum passes over the unconverged vectors */
+  double rqi_solve_tol; /* RQI: relative residual of each shifted solve */
+  int rayleigh_ritz;    /* RQI: 1 = Rayleigh-Ritz over all vectors after each sweep */
+  int rqi_guard;        /* RQI: vectors iterated beyond n_eig (guard band against
+                           missed modes); the n_eig smallest |lambda| are returned */
+} lq_mg_params;
+
+typedef struct {
+  int iters[16];        /* FGMRES iterations per right-hand side */
+  double relres[16];    /* final true relative residual per right-hand side */
+  int coarse_iters;     /* total coarse GMRES iterations in the call */
+} lq_solve_stats;
+
+typedef struct {
+  int sweeps;           /* passes of Alg. 1 over the unconverged vectors */
+  int solves;           /* shifted systems solved */
+  int fgmres_iters;     /* total FGMRES iterations */
+  int p_rebuilds;       /* interpolation / coarse-operator rebuilds */
+  double t_solve, t_ortho, t_rebuild, t_rq;   /* seconds per phase */
+} lq_rqi_stats;
+
+int lq_params_default(lq_mg_params *p);
+
+/* Create a context for a lattice.  dims: host int[4] (each >= 2); t_bc: -1
+ * antiperiodic or +1 periodic in t; hip_stream: hipStream_t the context
+ * issues all work on (NULL = default stream).  Errors: LQ_ERR_ARG. */
+int lq_create(lq_ctx **out, const int dims[4], int t_bc, void *hip_stream);
+int lq_destroy(lq_ctx *ctx);
+const char *lq_last_error(const lq_ctx *ctx);
+
+/* y = Q x for n_rhs fields (sec. 2: Q = gamma5 D).  U: device [4][9][V];
+ * x, y: device [n_rhs][12][V], must not overlap.  Asynchronous.
+ * Errors: LQ_ERR_ARG (NULL pointer, n_rhs < 1). */
+int q_apply(lq_ctx *ctx, const lq_c128 *U, double m0, const lq_c128 *x,
+            lq_c128 *y, int n_rhs);
+/* Single-precision variant: same layouts with complex64 elements. */
+int q_apply_c64(lq_ctx *ctx, const lq_c64 *U, double m0, const lq_c64 *x,
+                lq_c64 *y, int n_rhs);
+
+/* Adaptive multigrid setup (sec. 2.1) for Q(U, m0).  agg: host int[4] block
+ * extents of the aggregates (each divides the lattice extent; the number of
+ * blocks per direction is 1 or even, so that red/black SAP is well defined);
+ * n_tv: number Nv of test vectors (2*Nv coarse unknowns per aggregate,
+ * 1 <= Nv <= min(32, 6*prod(agg))).  tv0: device [n_tv][12][V] random start
+ * vectors (the method draws no random numbers itself).  p: NULL = defaults.
+ * Copies U; replaces any previous hierarchy.
+ * Errors: LQ_ERR_ARG, LQ_ERR_OOM, LQ_ERR_NUMERIC (locally dependent vectors). */
+int mg_setup(lq_ctx *ctx, const lq_c128 *U, double m0, const int agg[4],
+             int n_tv, const lq_c128 *tv0, const lq_mg_params *p);
+
+/* Solve (Q - sigma[k]) x[k] = rhs[k] for k < n_rhs (1..16) to the relative
+ * residual tol with FP64 flexible GMRES preconditioned by the multigrid cycle
+ * (sec. 2.2).  sigma: host double[n_rhs]; rhs, x: device [n_rhs][12][V].
+ * Uses the hierarchy as it stands (rqi_lowmodes rebuilds it from the
+ * eigenvector approximations).  st: may be NULL.
+ * Errors: LQ_ERR_STATE (no setup), LQ_ERR_ARG; LQ_WARN_NOCONV. */
+int mg_solve_shifted(lq_ctx *ctx, int n_rhs, const double *sigma,
+                     const lq_c128 *rhs, lq_c128 *x, double tol,
+                     lq_solve_stats *st);
+
+/* Lowest-|lambda| eigenpairs of Q by Alg. 1 (RQI + multigrid), to residual
+ * ||Q v - lambda v|| <= tol with ||v|| = 1.  The iteration works on
+ * n_work = n_eig + rqi_guard vectors.  Start vectors: the first min(Nv, n_work)
+ * setup test vectors, then the n_v0 = n_work - min(Nv, n_work) device fields
+ * V0 [n_v0][12][V]; if n_v0 == n_work, V0 replaces all start vectors (warm
+ * start).  With rayleigh_ritz = 1 the vectors are replaced by the Ritz
+ * vectors of their span after every sweep.  Stops when the n_eig vectors with
+ * smallest |lambda| have converged.  Output: lambda, resid host
+ * double[n_eig]; V device [n_eig][12][V]; sorted by (|lambda|, lambda).  The
+ * hierarchy is left built from the eigenvector approximations.
+ * Errors: LQ_ERR_STATE, LQ_ERR_ARG; LQ_WARN_NOCONV (sweep limit). */
+int rqi_lowmodes(lq_ctx *ctx, int n_eig, double tol, double *lambda,
+                 lq_c128 *V, double *resid, const lq_c128 *V0, int n_v0,
+                 lq_rqi_stats *st);
+
+/* ---- inspection of the hierarchy (parity tests; sec. 2 objects) ---------- */
+/* Number of test vectors Nv and aggregates nA of the current hierarchy. */
+int mg_info(lq_ctx *ctx, int *nv, int *n_agg);
+/* P as Nv canonical fields: device [Nv][12][V] c128; restricted to aggregate
+ * A and gamma5 half h the fields give the orthonormal columns (A, h, k). */
+int mg_get_interp(lq_ctx *ctx, lq_c128 *P);
+/* Q_c = P^dag Q P: device [nA][5][2Nv][2Nv] c128, block 0 = aggregate with
+ * itself, block 1 + mu = aggregate A with A + mu_hat (row index h*Nv + k of A,
+ * column index of the neighbour); the A - mu blocks are the conjugate
+ * transposes of the A - mu forward blocks (Q_c is Hermitian). */
+int mg_get_coarse(lq_ctx *ctx, lq_c128 *Qc);
+/* Restriction c = P^dag f: f device [n][12][V], c device [n][nA][2Nv]. */
+int mg_restrict(lq_ctx *ctx, int n, const lq_c128 *f, lq_c128 *c);
+/* Prolongation f = P c (shapes as above). */
+int mg_prolong(lq_ctx *ctx, int n, const lq_c128 *c, lq_c128 *f);
+/* y = (Q_c - sigma[k]) x[k] on coarse vectors [n][nA][2Nv]; sigma host. */
+int mg_coarse_apply(lq_ctx *ctx, int n, const double *sigma, const lq_c128 *x,
+                    lq_c128 *y);
+/* z = smoother applied to r for shifts sigma (steps as in the parameters'
+ * 'post'): SAP on D_sigma with rhs gamma5 r from z = 0.  Shapes [n][12][V]. */
+int mg_smooth(lq_ctx *ctx, int n, const double *sigma, const lq_c128 *r,
+              lq_c128 *z, int steps);
+/* z = B_sigma r, one multigrid cycle (eq. E_2g).  Shapes [n][12][V]. */
+int mg_cycle(lq_ctx *ctx, int n, const double *sigma, const lq_c128 *r,
+             lq_c128 *z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQMG_H */

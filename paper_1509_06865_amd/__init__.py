@@ -1,0 +1,7 @@
+"""MI355X (gfx950) eigensolver for the Hermitian Wilson-Dirac operator: RQI with
+gamma5-preserving aggregation multigrid (Bali et al., Lattice 2015, Alg. 1).
+
+The computation lives in the HIP library ``lib/liblqmg.so`` (C ABI in
+``include/lqmg.h``); ``lqmg`` is its ctypes binding.
+"""
+from .lqmg import Context, LQError, MGParams, PREC_FP64, PREC_MIXED, load, library_path  # noqa: F401

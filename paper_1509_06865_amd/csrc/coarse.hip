@@ -1,0 +1,84 @@
+// Coarse-grid operator Q_c = P^dag Q P (sec. 2): a nearest-neighbour stencil
+// on the lattice of aggregates with dense (2 Nv) x (2 Nv) complex blocks.
+// Stored blocks per coarse site: the self block and the four forward blocks;
+// the backward coupling from A - mu is the conjugate transpose of the
+// forward block of A - mu, because Q_c is Hermitian.
+#include "lq_kernels.h"
+
+namespace lq {
+namespace {
+
+__device__ inline int cnbr(const CoarseGeom &cg, int A, int mu, int step) {
+  int a[4], r = A;
+  for (int m = 0; m < 3; ++m) { a[m] = r % cg.nb[m]; r /= cg.nb[m]; }
+  a[3] = r;
+  a[mu] = (a[mu] + step + cg.nb[mu]) % cg.nb[mu];
+  return a[0] + cg.nb[0] * (a[1] + cg.nb[1] * (a[2] + cg.nb[2] * a[3]));
+}
+
+// One workgroup (one wave) per (coarse site, rhs); thread i computes row i.
+template <typename T>
+__global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
+                                                     const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
+                                                     Shifts sig, bool g5form) {
+  __shared__ cplx<T> xs[9][64];
+  const int A = blockIdx.x, k = blockIdx.y, i = threadIdx.x;
+  const int n2 = cg.n2;
+  const cplx<T> *x = xin + (long long)k * cg.nA * n2;
+  int nb[9];
+  nb[0] = A;
+  for (int mu = 0; mu < 4; ++mu) { nb[1 + mu] = cnbr(cg, A, mu, 1); nb[5 + mu] = cnbr(cg, A, mu, -1); }
+  if (i < n2)
+    for (int d = 0; d < 9; ++d) xs[d][i] = x[(long long)nb[d] * n2 + i];
+  __syncthreads();
+  if (i >= n2) return;
+  const long long bs = (long long)n2 * n2;
+  // self and forward blocks: row i of Qc[A][d]
+  cplx<T> acc = mk<T>(0, 0);
+  for (int d = 0; d < 5; ++d) {
+    const cplx<T> *M = Qc + ((long long)A * 5 + d) * bs + (long long)i * n2;
+    for (int j = 0; j < n2; ++j) acc = acc + M[j] * xs[d][j];
+  }
+  // backward: sum_j conj(Qc[A-mu][1+mu][j][i]) x_{A-mu}[j]
+  for (int mu = 0; mu < 4; ++mu) {
+    const cplx<T> *M = Qc + ((long long)nb[5 + mu] * 5 + 1 + mu) * bs + i;
+    for (int j = 0; j < n2; ++j) acc = acc + cmul_conj(M[(long long)j * n2], xs[5 + mu][j]);
+  }
+  acc = acc - (T)sig.s[k] * xs[0][i];
+  if (g5form && i >= n2 / 2) acc = -acc;
+  yout[((long long)k * cg.nA + A) * n2 + i] = acc;
+}
+
+template <typename T>
+__global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T> *__restrict__ y, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int i = (int)(e % cg.n2);
+  const cplx<T> v = x[e];
+  y[e] = (i >= cg.n2 / 2) ? -v : v;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig,
+                         int nrhs, bool g5form, hipStream_t st) {
+  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, g5form);
+  LQ_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nrhs, hipStream_t st) {
+  const long long n = (long long)nrhs * cg.nA * cg.n2;
+  hipLaunchKernelGGL((k_coarse_g5<T>), dim3(blocks_for(n, 256)), dim3(256), 0, st, cg, x, y, n);
+  LQ_HIP(hipGetLastError());
+}
+
+template void launch_coarse_apply<float>(const CoarseGeom &, const c64 *, const c64 *, c64 *, const Shifts &, int,
+                                         bool, hipStream_t);
+template void launch_coarse_apply<double>(const CoarseGeom &, const c128 *, const c128 *, c128 *, const Shifts &,
+                                          int, bool, hipStream_t);
+template void launch_coarse_g5<float>(const CoarseGeom &, const c64 *, c64 *, int, hipStream_t);
+template void launch_coarse_g5<double>(const CoarseGeom &, const c128 *, c128 *, int, hipStream_t);
+
+}  // namespace lq

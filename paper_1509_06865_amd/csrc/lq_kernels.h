@@ -1,0 +1,106 @@
+// Host-side launchers of the HIP kernels of liblqmg (one translation unit per
+// kernel family).  All pointers are device pointers; all launches are
+// asynchronous on the given stream.
+#pragma once
+#include "lq_common.h"
+
+namespace lq {
+
+struct Shifts { double s[kMaxRhs]; };
+
+// ---- Wilson stencil (wilson.hip) -------------------------------------------
+enum WilsonMode { W_QSHIFT = 0, W_RESID = 1 };
+// mode W_QSHIFT: y_k = (Q - sigma_k) x_k ; W_RESID: y_k = b_k - (Q - sigma_k) x_k
+template <typename T>
+void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y,
+                   const cplx<T> *b, double m0, const Shifts &sig, int nrhs, int mode,
+                   hipStream_t st);
+// Split hops of Q for the coarse operator.  Input: nf fields x (one column of
+// P each) whose gamma5 half 'half[j]' is used (the other half read as zero).
+// Output parts[j][5][12][V]: part 0 = gamma5[(4+m0) x - 1/2 sum_mu (hops that
+// stay inside a block)], part 1+mu = gamma5[-1/2 (forward mu hop leaving the block)].
+template <typename T>
+void launch_coarse_parts(const Geom &g, const cplx<T> *U, const cplx<T> *x, const int *half_dev,
+                         int nf, long long xstride, cplx<T> *parts, double m0, hipStream_t st);
+
+// ---- BLAS-1 (blas.hip) ------------------------------------------------------
+// Batched vectors: nrhs vectors of length n, vector k at base + k*stride.
+// Partial sums use a fixed reduction tree (deterministic).
+// out[i][k] = <v_i,k , w_k> for i < nv (basis vector i of rhs k at
+// vbase + i*vstride + k*rstride), w_k at w + k*wstride; vectors of n complex.
+template <typename T>
+void launch_dots(int nv, const cplx<T> *vbase, long long vstride, long long rstride,
+                 const cplx<T> *w, long long wstride, long long n, int nrhs,
+                 c128 *out /*device [nv][nrhs]*/, c128 *scratch, hipStream_t st,
+                 const int *active = nullptr /*device [nrhs]: skip systems with 0*/);
+// w_k += sign * sum_i h[i][k] v_i,k  (h device [nv][nrhs], FP64)
+template <typename T>
+void launch_multi_axpy(int nv, const cplx<T> *vbase, long long vstride, long long rstride,
+                       const c128 *h, cplx<T> *w, long long wstride, long long n, int nrhs,
+                       double sign, hipStream_t st, const int *active = nullptr);
+// Device-side GMRES bookkeeping (blas.hip), one thread per system: see there.
+void launch_arnoldi_start(int nrhs, int m, const c128 *nrm2, const double *bn, double tol, c128 *g, int *active,
+                          int *kk, c128 *coef, hipStream_t st);
+void launch_arnoldi_update(int j, int m, int nrhs, const c128 *h1, const c128 *h2, const c128 *nrm2, c128 *H,
+                           double *cs, c128 *sn, c128 *g, const double *bn, double tol, int *active, int *kk,
+                           c128 *coef, int *bad, hipStream_t st);
+void launch_arnoldi_solve(int m, int nrhs, const c128 *H, const c128 *g, const int *kk, c128 *Y, hipStream_t st);
+// Scratch size (in c128 elements) that launch_dots needs.
+size_t dots_scratch_elems(int nv, int nrhs);
+// y_k = a_k * x_k (+ y_k if accumulate), a device [nrhs] c128
+template <typename T>
+void launch_scale(const c128 *a, const cplx<T> *x, long long xstride, cplx<T> *y, long long ystride,
+                  long long n, int nrhs, bool accumulate, hipStream_t st);
+// y = x with precision change
+template <typename To, typename Ti>
+void launch_convert(const cplx<Ti> *x, cplx<To> *y, long long n, hipStream_t st);
+// canonical <-> blocked layout of [nf][12][V] fields
+template <typename T>
+void launch_permute(const Geom &blocked, const cplx<T> *x, cplx<T> *y, int nf, bool to_blocked,
+                    hipStream_t st);
+// links [4][9][V] canonical -> blocked with precision change
+template <typename To>
+void launch_pack_links(const Geom &blocked, const c128 *U, cplx<To> *out, hipStream_t st);
+
+// ---- SAP (sap.hip) ----------------------------------------------------------
+// One colour pass of multiplicative SAP on D_sigma = D - sigma gamma5 for
+// rhs gamma5 r:  z_B += MR_B(gamma5 r - D_sigma z) on every block B of
+// colour 'colour'.  Fields [nrhs][12][V] in the blocked layout (block = SAP block).
+template <typename T>
+void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T> *z,
+                       const int *blocks_of_colour, int nblocks, double m0, const Shifts &sig,
+                       int nrhs, int n_mr, hipStream_t st);
+
+// ---- transfers (transfer.hip) -----------------------------------------------
+// c[j][A][h*Nv + k] = sum_{x in A, s in h, col} conj(P_k[3s+col][x]) f_j[3s+col][x]
+template <typename T>
+void launch_restrict(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *f, long long fstride,
+                     int nf, cplx<T> *c, hipStream_t st);
+// f_j (+)= P c_j
+template <typename T>
+void launch_prolong(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *c, cplx<T> *f,
+                    long long fstride, int nf, bool accumulate, hipStream_t st);
+// P from test vectors W [Nv][12][V] (FP64, blocked): per block and gamma5
+// half, Cholesky-QR applied twice.  Writes P64 (and P32 if non-null).
+// status (device int) set to 1 if a local Gram matrix is not positive definite.
+void launch_build_P(const Geom &g, const c128 *W, int Nv, c128 *P64, int *status, hipStream_t st);
+// Q_c columns from restricted parts: parts_c[j][5][nA][2Nv] -> Qc[A][d][row][col_j]
+template <typename T>
+void launch_scatter_coarse(const cplx<T> *parts_c, int nf, const int *cols_host, int n2,
+                           int nA, cplx<T> *Qc, hipStream_t st);
+
+// ---- coarse level (coarse.hip) ------------------------------------------------
+struct CoarseGeom {
+  int nb[4];       // coarse lattice extents (blocks per direction)
+  int nA;          // coarse sites
+  int n2;          // 2 * Nv unknowns per coarse site
+};
+// y_k = g5c^e (Q_c - sigma_k) x_k (e = 1 if gamma5c form); vectors [nrhs][nA][n2]
+template <typename T>
+void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y,
+                         const Shifts &sig, int nrhs, bool g5form, hipStream_t st);
+// y_k = g5c x_k (elementwise)
+template <typename T>
+void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nrhs, hipStream_t st);
+
+}  // namespace lq

@@ -1,0 +1,1063 @@
+// Host side of liblqmg: the context, batched (flexible) GMRES, the multigrid
+// cycle and setup, Rayleigh quotient iteration (Alg. 1) and the C ABI.
+// Every numerical step runs in the HIP kernels of this library; the host only
+// keeps the small Hessenberg / Givens state of the Krylov solvers, the
+// eigenvalue bookkeeping of Alg. 1 and the control flow.
+#include "lqmg.h"
+#include "lq_kernels.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+using namespace lq;
+using cd = std::complex<double>;
+
+namespace {
+
+struct ApiError {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &m) { throw ApiError{code, m}; }
+
+template <typename T> struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  T *get(size_t count) {
+    if (count <= n && p) return p;
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(LQ_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+    return p;
+  }
+};
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T> struct MGData {
+  DevBuf<cplx<T>> U;    // blocked links (T precision)
+  DevBuf<cplx<T>> P;    // [Nv][12][V]
+  DevBuf<cplx<T>> Qc;   // [nA][5][n2][n2]
+};
+
+// Device-side state of one batched GMRES: Hessenberg columns, Givens
+// rotations, per-system activity and the reduction outputs.
+struct KState {
+  DevBuf<c128> bH, bsn, bg, bh1, bh2, bnrm, bcoef, bY;
+  DevBuf<double> bcs, bbn;
+  DevBuf<int> bact, bkk, bbad;
+  c128 *H, *sn, *g, *h1, *h2, *nrm2, *coef, *Y;
+  double *cs, *bn;
+  int *active, *kk, *bad;
+  void alloc(int m, int nrhs) {
+    H = bH.get((size_t)nrhs * (m + 1) * m);
+    sn = bsn.get((size_t)nrhs * m);
+    g = bg.get((size_t)nrhs * (m + 1));
+    h1 = bh1.get((size_t)(m + 1) * nrhs);
+    h2 = bh2.get((size_t)(m + 1) * nrhs);
+    nrm2 = bnrm.get(nrhs);
+    coef = bcoef.get(nrhs);
+    Y = bY.get((size_t)m * nrhs);
+    cs = bcs.get((size_t)nrhs * m);
+    bn = bbn.get(nrhs);
+    active = bact.get(nrhs);
+    kk = bkk.get(nrhs);
+    bad = bbad.get(1);
+  }
+};
+
+// Work vectors of one batched Krylov solve.
+template <typename T> struct KrylovWork {
+  DevBuf<cplx<T>> V, Z, r;
+  DevBuf<c128> scratch;
+  KState st;
+};
+
+}  // namespace
+
+struct lq_ctx {
+  int L[4];
+  int tbc;
+  hipStream_t st;
+  std::string err;
+  Geom gcan;
+  int dev;
+
+  bool have = false;
+  lq_mg_params p;
+  double m0 = 0;
+  int Nv = 0;
+  int agg[4];
+  Geom g;
+  CoarseGeom cg;
+  DevBuf<c128> U64;                 // blocked FP64 links (outer operator)
+  MGData<double> d64;
+  MGData<float> d32;
+  DevBuf<c128> W;                   // test vectors, blocked, FP64
+  DevBuf<c128> P64;                 // P in FP64 (source of the FP32 copy)
+  DevBuf<int> blocks[2];
+  int nblocks[2] = {0, 0};
+  DevBuf<int> status;
+  DevBuf<c128> red_scratch, red_out, coef;
+  DevBuf<int> ints;                 // small per-call integer arrays
+  // workspaces
+  KrylovWork<double> fine_kw;
+  KrylovWork<double> coarse_kw64;
+  KrylovWork<float> coarse_kw32;
+  DevBuf<c128> tmpA, tmpB;          // FP64 fine work
+  DevBuf<c64> f32a, f32b, f32c;     // FP32 fine work (mixed cycle)
+  DevBuf<c128> f64a, f64b;          // FP64 fine work (cycle)
+  DevBuf<c128> c64a, c64b;          // coarse work (FP64)
+  DevBuf<c64> c32a, c32b;           // coarse work (FP32)
+  DevBuf<c128> parts64, pc64;
+  DevBuf<c64> parts32, pc32;
+  DevBuf<c128> eig;                 // RQI vectors, blocked FP64 [n][12][V]
+  DevBuf<c128> sel;                 // vectors that build P [Nv][12][V]
+  DevBuf<c128> rr_buf;              // Rayleigh-Ritz rotated vectors
+  DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
+  int coarse_iters = 0;
+};
+
+namespace {
+
+void sync(lq_ctx *c) { LQ_HIP(hipStreamSynchronize(c->st)); }
+
+template <typename T> void zero(lq_ctx *c, cplx<T> *p, size_t n) {
+  LQ_HIP(hipMemsetAsync(p, 0, n * sizeof(cplx<T>), c->st));
+}
+template <typename T> void copy(lq_ctx *c, cplx<T> *dst, const cplx<T> *src, size_t n) {
+  LQ_HIP(hipMemcpyAsync(dst, src, n * sizeof(cplx<T>), hipMemcpyDeviceToDevice, c->st));
+}
+
+// Inner products <v_i,k, w_k>, returned to the host as [nv][nrhs].
+template <typename T>
+std::vector<cd> dots(lq_ctx *c, int nv, const cplx<T> *vbase, long long vstride, long long rstride,
+                     const cplx<T> *w, long long wstride, long long n, int nrhs) {
+  std::vector<cd> out((size_t)nv * nrhs);
+  if (nv == 0) return out;
+  c128 *sc = c->red_scratch.get(dots_scratch_elems(nv, nrhs));
+  c128 *o = c->red_out.get((size_t)nv * nrhs);
+  launch_dots<T>(nv, vbase, vstride, rstride, w, wstride, n, nrhs, o, sc, c->st);
+  LQ_HIP(hipMemcpyAsync(out.data(), o, out.size() * sizeof(c128), hipMemcpyDeviceToHost, c->st));
+  sync(c);
+  return out;
+}
+
+// w_k += sign * sum_i h[i][k] v_i,k with h given on the host
+template <typename T>
+void axpys(lq_ctx *c, int nv, const cplx<T> *vbase, long long vstride, long long rstride,
+           const std::vector<cd> &h, cplx<T> *w, long long wstride, long long n, int nrhs, double sign) {
+  if (nv == 0) return;
+  c128 *d = c->coef.get((size_t)nv * nrhs);
+  LQ_HIP(hipMemcpyAsync(d, h.data(), (size_t)nv * nrhs * sizeof(c128), hipMemcpyHostToDevice, c->st));
+  launch_multi_axpy<T>(nv, vbase, vstride, rstride, d, w, wstride, n, nrhs, sign, c->st);
+  sync(c);   // the host vector h may be released after return
+}
+
+template <typename T>
+void scale(lq_ctx *c, const std::vector<cd> &a, const cplx<T> *x, long long xs, cplx<T> *y, long long ys,
+           long long n, int nrhs, bool acc) {
+  c128 *d = c->coef.get((size_t)nrhs);
+  LQ_HIP(hipMemcpyAsync(d, a.data(), (size_t)nrhs * sizeof(c128), hipMemcpyHostToDevice, c->st));
+  launch_scale<T>(d, x, xs, y, ys, n, nrhs, acc, c->st);
+  sync(c);
+}
+
+template <typename T>
+std::vector<double> norms(lq_ctx *c, const cplx<T> *w, long long n, int nrhs) {
+  std::vector<double> r(nrhs);
+  for (int k = 0; k < nrhs; ++k) {
+    auto d = dots<T>(c, 1, w + k * n, 0, 0, w + k * n, 0, n, 1);
+    r[k] = std::sqrt(std::max(0.0, d[0].real()));
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Batched restarted (flexible) GMRES from x = 0.  nrhs independent systems
+// share every kernel launch; each keeps its own Hessenberg matrix and stops on
+// its own.  Orthogonalisation: classical Gram-Schmidt applied twice.
+// ---------------------------------------------------------------------------
+template <typename T> struct KOps {
+  std::function<void(const cplx<T> *, cplx<T> *)> apply;                       // y = A x
+  std::function<void(const cplx<T> *, cplx<T> *)> precond;                     // z = M v, may be empty
+  std::function<void(const cplx<T> *, const cplx<T> *, cplx<T> *)> resid;      // r = b - A x
+};
+
+template <typename T>
+bool gmres_batched(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KOps<T> &ops, const cplx<T> *b,
+                   cplx<T> *x, int m, int max_restarts, double tol, int *iters, double *relres,
+                   int check_every) {
+  // All Arnoldi bookkeeping stays on the device; the host waits only once per
+  // restart cycle, and in between every check_every steps to stop early.
+  const bool flex = (bool)ops.precond;
+  cplx<T> *Vb = kw.V.get((size_t)(m + 1) * nrhs * n);
+  cplx<T> *Zb = flex ? kw.Z.get((size_t)m * nrhs * n) : nullptr;
+  cplx<T> *r = kw.r.get((size_t)nrhs * n);
+  KState &S = kw.st;
+  S.alloc(m, nrhs);
+  LQ_HIP(hipMemsetAsync(S.bad, 0, sizeof(int), c->st));
+  const long long vs = (long long)nrhs * n;     // stride between basis vectors
+  c128 *sc = kw.scratch.get(dots_scratch_elems(m + 1, nrhs));
+  // ||b_k||
+  launch_dots<T>(1, b, 0, n, b, n, n, nrhs, S.nrm2, sc, c->st);
+  std::vector<c128> h_nrm(nrhs);
+  LQ_HIP(hipMemcpyAsync(h_nrm.data(), S.nrm2, nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->st));
+  sync(c);
+  std::vector<double> bn(nrhs), beta(nrhs);
+  for (int k = 0; k < nrhs; ++k) bn[k] = beta[k] = std::sqrt(std::max(0.0, h_nrm[k].re));
+  LQ_HIP(hipMemcpyAsync(S.bn, bn.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c->st));
+  zero<T>(c, x, (size_t)nrhs * n);
+  copy<T>(c, r, b, (size_t)nrhs * n);
+  std::vector<int> it(nrhs, 0), kk(nrhs), act(nrhs);
+  bool all_conv = true;
+  for (int cyc = 0; cyc <= max_restarts; ++cyc) {
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) any = any || (bn[k] > 0 && beta[k] > tol * bn[k]);
+    if (!any) break;
+    // S.nrm2 holds ||r_k||^2 here
+    launch_arnoldi_start(nrhs, m, S.nrm2, S.bn, tol, S.g, S.active, S.kk, S.coef, c->st);
+    launch_scale<T>(S.coef, r, n, Vb, n, n, nrhs, false, c->st);
+    for (int j = 0; j < m; ++j) {
+      if (check_every > 0 && j > 0 && j % check_every == 0) {
+        LQ_HIP(hipMemcpyAsync(act.data(), S.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        bool run = false;
+        for (int k = 0; k < nrhs; ++k) run = run || act[k];
+        if (!run) break;
+      }
+      cplx<T> *vj = Vb + j * vs, *w = Vb + (j + 1) * vs;
+      const cplx<T> *src = vj;
+      if (flex) {
+        ops.precond(vj, Zb + j * vs);
+        src = Zb + j * vs;
+      }
+      ops.apply(src, w);
+      launch_dots<T>(j + 1, Vb, vs, n, w, n, n, nrhs, S.h1, sc, c->st, S.active);
+      launch_multi_axpy<T>(j + 1, Vb, vs, n, S.h1, w, n, n, nrhs, -1.0, c->st, S.active);
+      launch_dots<T>(j + 1, Vb, vs, n, w, n, n, nrhs, S.h2, sc, c->st, S.active);
+      launch_multi_axpy<T>(j + 1, Vb, vs, n, S.h2, w, n, n, nrhs, -1.0, c->st, S.active);
+      launch_dots<T>(1, w, 0, n, w, n, n, nrhs, S.nrm2, sc, c->st, S.active);
+      launch_arnoldi_update(j, m, nrhs, S.h1, S.h2, S.nrm2, S.H, S.cs, S.sn, S.g, S.bn, tol, S.active, S.kk, S.coef,
+                            S.bad, c->st);
+      launch_scale<T>(S.coef, w, n, w, n, n, nrhs, false, c->st);
+    }
+    // x += sum_i y_i (Z_i or V_i)
+    launch_arnoldi_solve(m, nrhs, S.H, S.g, S.kk, S.Y, c->st);
+    launch_multi_axpy<T>(m, flex ? Zb : Vb, vs, n, S.Y, x, n, n, nrhs, 1.0, c->st);
+    ops.resid(b, x, r);
+    launch_dots<T>(1, r, 0, n, r, n, n, nrhs, S.nrm2, sc, c->st);
+    LQ_HIP(hipMemcpyAsync(h_nrm.data(), S.nrm2, nrhs * sizeof(c128), hipMemcpyDeviceToHost, c->st));
+    LQ_HIP(hipMemcpyAsync(kk.data(), S.kk, nrhs * sizeof(int), hipMemcpyDeviceToHost, c->st));
+    int bad = 0;
+    LQ_HIP(hipMemcpyAsync(&bad, S.bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    if (bad) fail(LQ_ERR_NUMERIC, "non-finite Krylov vector");
+    for (int k = 0; k < nrhs; ++k) {
+      beta[k] = std::sqrt(std::max(0.0, h_nrm[k].re));
+      if (!std::isfinite(beta[k])) fail(LQ_ERR_NUMERIC, "non-finite residual");
+      it[k] += kk[k];
+    }
+  }
+  for (int k = 0; k < nrhs; ++k) {
+    const double rr = bn[k] > 0 ? beta[k] / bn[k] : 0.0;
+    if (iters) iters[k] = it[k];
+    if (relres) relres[k] = rr;
+    if (rr > tol) all_conv = false;
+  }
+  return all_conv;
+}
+
+// ---------------------------------------------------------------------------
+// multigrid pieces in precision T
+// ---------------------------------------------------------------------------
+template <typename T> MGData<T> &mgd(lq_ctx *c);
+template <> MGData<double> &mgd<double>(lq_ctx *c) { return c->d64; }
+template <> MGData<float> &mgd<float>(lq_ctx *c) { return c->d32; }
+template <typename T> KrylovWork<T> &ckw(lq_ctx *c);
+template <> KrylovWork<double> &ckw<double>(lq_ctx *c) { return c->coarse_kw64; }
+template <> KrylovWork<float> &ckw<float>(lq_ctx *c) { return c->coarse_kw32; }
+
+Shifts shifts_of(const double *s, int n) {
+  Shifts S;
+  for (int k = 0; k < kMaxRhs; ++k) S.s[k] = (k < n && s) ? s[k] : 0.0;
+  return S;
+}
+
+// z = SAP steps on (Q - sigma) z = r, continuing from the current z
+template <typename T>
+void sap(lq_ctx *c, const double *sig, const cplx<T> *r, cplx<T> *z, int nrhs, int steps) {
+  Shifts S = shifts_of(sig, nrhs);
+  for (int s = 0; s < steps; ++s)
+    for (int col = 0; col < 2; ++col)
+      if (c->nblocks[col] > 0)
+        launch_sap_colour<T>(c->g, mgd<T>(c).U.p, r, z, c->blocks[col].p, c->nblocks[col], c->m0, S, nrhs,
+                             c->p.sap_mr, c->st);
+}
+
+template <typename T>
+void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, int nrhs, cplx<T> *rhs_buf) {
+  const long long n = (long long)c->cg.nA * c->cg.n2;
+  Shifts S = shifts_of(sig, nrhs);
+  launch_coarse_g5<T>(c->cg, rc, rhs_buf, nrhs, c->st);
+  KOps<T> ops;
+  const cplx<T> *Qc = mgd<T>(c).Qc.p;
+  ops.apply = [=](const cplx<T> *x, cplx<T> *y) { launch_coarse_apply<T>(c->cg, Qc, x, y, S, nrhs, true, c->st); };
+  auto &kw = ckw<T>(c);
+  const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
+  ops.resid = [=](const cplx<T> *b, const cplx<T> *x, cplx<T> *r) {
+    launch_coarse_apply<T>(c->cg, Qc, x, r, S, nrhs, true, c->st);
+    launch_scale<T>(pm1, r, n, r, n, n, nrhs, false, c->st);                 // r = -A x
+    launch_multi_axpy<T>(1, b, 0, n, pp1, r, n, n, nrhs, 1.0, c->st);       // r += b
+  };
+  int its[kMaxRhs];
+  gmres_batched<T>(c, kw, n, nrhs, ops, rhs_buf, ec, c->p.coarse_m, c->p.coarse_restarts, c->p.coarse_tol, its,
+                   nullptr, 8);
+  for (int k = 0; k < nrhs; ++k) c->coarse_iters += its[k];
+}
+
+template <typename T> struct CycleBufs { cplx<T> *tmp, *rc, *ec, *cb; };
+
+template <typename T> CycleBufs<T> cycle_bufs(lq_ctx *c, int nrhs);
+template <> CycleBufs<double> cycle_bufs<double>(lq_ctx *c, int nrhs) {
+  const size_t nf = (size_t)nrhs * 12 * c->g.V, nc = (size_t)nrhs * c->cg.nA * c->cg.n2;
+  c128 *cbuf = c->c64a.get(3 * nc);
+  return {c->f64a.get(nf), cbuf, cbuf + nc, cbuf + 2 * nc};
+}
+template <> CycleBufs<float> cycle_bufs<float>(lq_ctx *c, int nrhs) {
+  const size_t nf = (size_t)nrhs * 12 * c->g.V, nc = (size_t)nrhs * c->cg.nA * c->cg.n2;
+  c64 *cbuf = c->c32a.get(3 * nc);
+  return {c->f32c.get(nf), cbuf, cbuf + nc, cbuf + 2 * nc};
+}
+
+// z = B_sigma r: one multigrid cycle (eq. E_2g) in precision T.
+template <typename T>
+void cycle(lq_ctx *c, const double *sig, const cplx<T> *r, cplx<T> *z, int nrhs) {
+  const size_t nf = (size_t)nrhs * 12 * c->g.V;
+  CycleBufs<T> b = cycle_bufs<T>(c, nrhs);
+  auto &d = mgd<T>(c);
+  zero<T>(c, z, nf);
+  const cplx<T> *rr = r;
+  if (c->p.pre > 0) {
+    sap<T>(c, sig, r, z, nrhs, c->p.pre);
+    launch_wilson<T>(c->g, d.U.p, z, b.tmp, r, c->m0, shifts_of(sig, nrhs), nrhs, W_RESID, c->st);
+    rr = b.tmp;
+  }
+  launch_restrict<T>(c->g, d.P.p, c->Nv, rr, 12LL * c->g.V, nrhs, b.rc, c->st);
+  coarse_solve<T>(c, sig, b.rc, b.ec, nrhs, b.cb);
+  launch_prolong<T>(c->g, d.P.p, c->Nv, b.ec, z, 12LL * c->g.V, nrhs, true, c->st);
+  if (c->p.post > 0) sap<T>(c, sig, r, z, nrhs, c->p.post);
+}
+
+// z = B_sigma v with FP64 input/output; the cycle runs in the configured precision.
+void precond64(lq_ctx *c, const double *sig, const c128 *v, c128 *z, int nrhs) {
+  if (c->p.precision == LQ_PREC_FP64) {
+    cycle<double>(c, sig, v, z, nrhs);
+  } else {
+    const size_t nf = (size_t)nrhs * 12 * c->g.V;
+    c64 *v32 = c->f32a.get(nf), *z32 = c->f32b.get(nf);
+    launch_convert<float, double>(v, v32, (long long)nf, c->st);
+    cycle<float>(c, sig, v32, z32, nrhs);
+    launch_convert<double, float>(z32, z, (long long)nf, c->st);
+  }
+}
+
+// smoother only (FP64 interface), from z = 0
+void smooth64(lq_ctx *c, const double *sig, const c128 *r, c128 *z, int nrhs, int steps) {
+  const size_t nf = (size_t)nrhs * 12 * c->g.V;
+  if (c->p.precision == LQ_PREC_FP64) {
+    zero<double>(c, z, nf);
+    sap<double>(c, sig, r, z, nrhs, steps);
+  } else {
+    c64 *r32 = c->f32a.get(nf), *z32 = c->f32b.get(nf);
+    launch_convert<float, double>(r, r32, (long long)nf, c->st);
+    zero<float>(c, z32, nf);
+    sap<float>(c, sig, r32, z32, nrhs, steps);
+    launch_convert<double, float>(z32, z, (long long)nf, c->st);
+  }
+}
+
+// Q_c = P^dag Q P in precision T from P_T and U_T.
+template <typename T> void build_coarse(lq_ctx *c, DevBuf<cplx<T>> &parts, DevBuf<cplx<T>> &pc) {
+  auto &d = mgd<T>(c);
+  const int Nv = c->Nv, n2 = 2 * Nv, nA = c->cg.nA;
+  const long long V12 = 12LL * c->g.V;
+  const int C = std::min(Nv, 8);
+  cplx<T> *pa = parts.get((size_t)C * 5 * V12);
+  cplx<T> *pcb = pc.get((size_t)C * 5 * nA * n2);
+  cplx<T> *Qc = d.Qc.get((size_t)nA * 5 * n2 * n2);
+  int *dint = c->ints.get(2 * C);
+  for (int h = 0; h < 2; ++h)
+    for (int l0 = 0; l0 < Nv; l0 += C) {
+      const int nc = std::min(C, Nv - l0);
+      std::vector<int> hi(2 * C);
+      for (int j = 0; j < nc; ++j) { hi[j] = h; hi[C + j] = h * Nv + l0 + j; }
+      LQ_HIP(hipMemcpyAsync(dint, hi.data(), 2 * C * sizeof(int), hipMemcpyHostToDevice, c->st));
+      launch_coarse_parts<T>(c->g, d.U.p, d.P.p + l0 * V12, dint, nc, V12, pa, c->m0, c->st);
+      launch_restrict<T>(c->g, d.P.p, Nv, pa, V12, 5 * nc, pcb, c->st);
+      launch_scatter_coarse<T>(pcb, nc, dint + C, n2, nA, Qc, c->st);
+      sync(c);
+    }
+}
+
+// P and Q_c from the FP64 fields src [Nv][12][V] (blocked)
+void rebuild(lq_ctx *c, const c128 *src) {
+  const size_t nP = (size_t)c->Nv * 12 * c->g.V;
+  int *st = c->status.get(1);
+  LQ_HIP(hipMemsetAsync(st, 0, sizeof(int), c->st));
+  c128 *P64 = c->P64.get(nP);
+  launch_build_P(c->g, src, c->Nv, P64, st, c->st);
+  int h_st = 0;
+  LQ_HIP(hipMemcpyAsync(&h_st, st, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  sync(c);
+  if (h_st) fail(LQ_ERR_NUMERIC, "test vectors are linearly dependent on an aggregate");
+  if (c->p.precision == LQ_PREC_FP64) {
+    copy<double>(c, c->d64.P.get(nP), P64, nP);
+    build_coarse<double>(c, c->parts64, c->pc64);
+  } else {
+    launch_convert<float, double>(P64, c->d32.P.get(nP), (long long)nP, c->st);
+    build_coarse<float>(c, c->parts32, c->pc32);
+  }
+  sync(c);
+}
+
+// Gram-Schmidt (twice) of n fields in place, in index order; FP64.
+void orthonormalise(lq_ctx *c, c128 *F, int n) {
+  const long long L = 12LL * c->g.V;
+  for (int k = 0; k < n; ++k) {
+    for (int pass = 0; pass < 2; ++pass) {
+      auto h = dots<double>(c, k, F, L, 0, F + k * L, 0, L, 1);
+      axpys<double>(c, k, F, L, 0, h, F + k * L, 0, L, 1, -1.0);
+    }
+    auto nr = norms<double>(c, F + k * L, L, 1);
+    if (!(nr[0] > 0) || !std::isfinite(nr[0])) fail(LQ_ERR_NUMERIC, "vector collapsed in Gram-Schmidt");
+    scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, F + k * L, 0, F + k * L, 0, L, 1, false);
+  }
+}
+
+// FGMRES for (Q - sigma_k) x_k = b_k, FP64, blocked layout.
+bool solve_shifted(lq_ctx *c, int nrhs, const double *sig, const c128 *b, c128 *x, double tol, int *iters,
+                   double *relres) {
+  const long long n = 12LL * c->g.V;
+  Shifts S = shifts_of(sig, nrhs);
+  std::vector<double> sv(sig, sig + nrhs);
+  KOps<double> ops;
+  ops.apply = [=](const c128 *in, c128 *out) {
+    launch_wilson<double>(c->g, c->U64.p, in, out, nullptr, c->m0, S, nrhs, W_QSHIFT, c->st);
+  };
+  ops.precond = [=](const c128 *in, c128 *out) { precond64(c, sv.data(), in, out, nrhs); };
+  ops.resid = [=](const c128 *bb, const c128 *xx, c128 *r) {
+    launch_wilson<double>(c->g, c->U64.p, xx, r, bb, c->m0, S, nrhs, W_RESID, c->st);
+  };
+  return gmres_batched<double>(c, c->fine_kw, n, nrhs, ops, b, x, c->p.fgmres_m, c->p.fgmres_restarts, tol, iters,
+                               relres, 1);
+}
+
+// Eigen-decomposition of a Hermitian n x n matrix (row-major) by cyclic
+// Jacobi rotations: on return A is diagonal (the eigenvalues) and the columns
+// of Vm are the eigenvectors.  Each step first rotates the phase of column q
+// so that A[p][q] is real, then applies the real symmetric Jacobi rotation.
+void jacobi_eigh(int n, std::vector<cd> &A, std::vector<cd> &Vm) {
+  Vm.assign((size_t)n * n, cd(0));
+  for (int i = 0; i < n; ++i) Vm[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> cd & { return A[(size_t)i * n + j]; };
+  auto v = [&](int i, int j) -> cd & { return Vm[(size_t)i * n + j]; };
+  double scale = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) scale += std::norm(a(i, j));
+  scale = std::sqrt(scale);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += std::norm(a(i, j));
+    if (std::sqrt(off) <= 1e-16 * scale) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double r = std::abs(a(p, q));
+        if (r <= 1e-300) continue;
+        const cd ph = std::conj(a(p, q)) / r;          // column q times ph, row q times conj(ph)
+        for (int k = 0; k < n; ++k) { a(k, q) *= ph; v(k, q) *= ph; }
+        for (int k = 0; k < n; ++k) a(q, k) *= std::conj(ph);
+        const double apq = a(p, q).real();
+        const double tau = (a(q, q).real() - a(p, p).real()) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double cth = 1.0 / std::sqrt(1.0 + t * t), sth = t * cth;
+        for (int k = 0; k < n; ++k) {
+          const cd kp = a(k, p), kq = a(k, q);
+          a(k, p) = cth * kp - sth * kq;
+          a(k, q) = sth * kp + cth * kq;
+          const cd vp = v(k, p), vq = v(k, q);
+          v(k, p) = cth * vp - sth * vq;
+          v(k, q) = sth * vp + cth * vq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const cd pk = a(p, k), qk = a(q, k);
+          a(p, k) = cth * pk - sth * qk;
+          a(q, k) = sth * pk + cth * qk;
+        }
+        a(p, q) = 0;
+        a(q, p) = 0;
+      }
+  }
+}
+
+// Rayleigh-Ritz on span(E) (E orthonormal, n fields): H = E^dag Q E, H = C w C^dag,
+// E <- E C ordered by (|w|, w); lam receives w.
+void rayleigh_ritz(lq_ctx *c, c128 *E, int n, std::vector<double> &lam) {
+  const long long V12 = 12LL * c->g.V;
+  c128 *QE = c->tmpA.get((size_t)kMaxRhs * V12);
+  std::vector<cd> H((size_t)n * n);
+  Shifts z = shifts_of(nullptr, 0);
+  for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, n - j0);
+    launch_wilson<double>(c->g, c->U64.p, E + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+    auto d = dots<double>(c, n, E, V12, 0, QE, V12, V12, nk);     // d[i][k] = <E_i, Q E_{j0+k}>
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < nk; ++k) H[(size_t)i * n + j0 + k] = d[(size_t)i * nk + k];
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) {
+      const cd h = 0.5 * (H[(size_t)i * n + j] + std::conj(H[(size_t)j * n + i]));
+      H[(size_t)i * n + j] = h;
+      H[(size_t)j * n + i] = std::conj(h);
+    }
+  std::vector<cd> Cm;
+  jacobi_eigh(n, H, Cm);
+  std::vector<int> o(n);
+  for (int i = 0; i < n; ++i) o[i] = i;
+  std::sort(o.begin(), o.end(), [&](int a, int b) {
+    const double wa = H[(size_t)a * n + a].real(), wb = H[(size_t)b * n + b].real();
+    if (std::fabs(wa) != std::fabs(wb)) return std::fabs(wa) < std::fabs(wb);
+    return wa < wb;
+  });
+  // new E_j = sum_i C[i][o_j] E_i, written to a second buffer, then copied back
+  c128 *NE = c->rr_buf.get((size_t)n * V12);
+  zero<double>(c, NE, (size_t)n * V12);
+  for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, n - j0);
+    std::vector<cd> h((size_t)n * nk);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < nk; ++k) h[(size_t)i * nk + k] = Cm[(size_t)i * n + o[j0 + k]];
+    axpys<double>(c, n, E, V12, 0, h, NE + j0 * V12, V12, V12, nk, 1.0);
+  }
+  copy<double>(c, E, NE, (size_t)n * V12);
+  for (int j = 0; j < n; ++j) lam[j] = H[(size_t)o[j] * n + o[j]].real();
+  sync(c);
+}
+
+void check_ctx(lq_ctx *c) {
+  if (!c) fail(LQ_ERR_ARG, "NULL context");
+  LQ_HIP(hipSetDevice(c->dev));
+}
+void need_mg(lq_ctx *c) {
+  check_ctx(c);
+  if (!c->have) fail(LQ_ERR_STATE, "mg_setup has not been called");
+}
+
+int guard(lq_ctx *c, const std::function<int()> &f) {
+  try {
+    if (c) c->err.clear();
+    return f();
+  } catch (const ApiError &e) {
+    if (c) c->err = e.msg;
+    return e.code;
+  } catch (const HipError &e) {
+    if (c) c->err = std::string("HIP error ") + hipGetErrorString(e.err) + " in " + e.what + " (" + e.file + ":" +
+                    std::to_string(e.line) + ")";
+    return LQ_ERR_HIP;
+  } catch (const std::exception &e) {
+    if (c) c->err = e.what();
+    return LQ_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+int lq_params_default(lq_mg_params *p) {
+  if (!p) return LQ_ERR_ARG;
+  p->precision = LQ_PREC_MIXED;
+  p->smoother = LQ_SMOOTH_SAP;
+  p->pre = 0;
+  p->post = 3;
+  p->sap_mr = 4;
+  p->gmres_smooth_m = 8;
+  p->coarse_m = 40;
+  p->coarse_restarts = 4;
+  p->coarse_tol = 0.05;
+  p->fgmres_m = 10;
+  p->fgmres_restarts = 40;
+  p->n_init = 2;
+  p->n_setup = 4;
+  p->rqi_block = 16;
+  p->rqi_max_sweeps = 30;
+  p->rqi_solve_tol = 1e-8;
+  p->rayleigh_ritz = 1;
+  p->rqi_guard = 2;
+  return LQ_OK;
+}
+
+int lq_create(lq_ctx **out, const int dims[4], int t_bc, void *stream) {
+  if (!out || !dims) return LQ_ERR_ARG;
+  *out = nullptr;
+  for (int m = 0; m < 4; ++m)
+    if (dims[m] < 2) return LQ_ERR_ARG;
+  if (t_bc != 1 && t_bc != -1) return LQ_ERR_ARG;
+  long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V * 12 > (1LL << 31) - 1) return LQ_ERR_ARG;
+  lq_ctx *c = new lq_ctx();
+  for (int m = 0; m < 4; ++m) c->L[m] = dims[m];
+  c->tbc = t_bc;
+  c->st = (hipStream_t)stream;
+  c->gcan = make_geom(dims, dims, t_bc);
+  if (hipGetDevice(&c->dev) != hipSuccess) { delete c; return LQ_ERR_HIP; }
+  lq_params_default(&c->p);
+  int rc = guard(c, [&] {
+    std::vector<c128> m1(kMaxRhs, c128{-1.0, 0.0}), p1(kMaxRhs, c128{1.0, 0.0});
+    LQ_HIP(hipMemcpy(c->minus_one.get(kMaxRhs), m1.data(), kMaxRhs * sizeof(c128), hipMemcpyHostToDevice));
+    LQ_HIP(hipMemcpy(c->plus_one.get(kMaxRhs), p1.data(), kMaxRhs * sizeof(c128), hipMemcpyHostToDevice));
+    return LQ_OK;
+  });
+  if (rc != LQ_OK) { delete c; return rc; }
+  *out = c;
+  return LQ_OK;
+}
+
+int lq_destroy(lq_ctx *c) {
+  if (!c) return LQ_ERR_ARG;
+  (void)hipSetDevice(c->dev);
+  (void)hipStreamSynchronize(c->st);
+  delete c;
+  return LQ_OK;
+}
+
+const char *lq_last_error(const lq_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+int q_apply(lq_ctx *c, const lq_c128 *U, double m0, const lq_c128 *x, lq_c128 *y, int n_rhs) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !x || !y || n_rhs < 1) fail(LQ_ERR_ARG, "q_apply: NULL pointer or n_rhs < 1");
+    Shifts S = shifts_of(nullptr, 0);
+    const long long L = 12LL * c->gcan.V;
+    for (int k0 = 0; k0 < n_rhs; k0 += kMaxRhs) {
+      const int nk = std::min(kMaxRhs, n_rhs - k0);
+      launch_wilson<double>(c->gcan, (const c128 *)U, (const c128 *)x + k0 * L, (c128 *)y + k0 * L, nullptr, m0, S,
+                            nk, W_QSHIFT, c->st);
+    }
+    return LQ_OK;
+  });
+}
+
+int q_apply_c64(lq_ctx *c, const lq_c64 *U, double m0, const lq_c64 *x, lq_c64 *y, int n_rhs) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !x || !y || n_rhs < 1) fail(LQ_ERR_ARG, "q_apply_c64: NULL pointer or n_rhs < 1");
+    Shifts S = shifts_of(nullptr, 0);
+    const long long L = 12LL * c->gcan.V;
+    for (int k0 = 0; k0 < n_rhs; k0 += kMaxRhs) {
+      const int nk = std::min(kMaxRhs, n_rhs - k0);
+      launch_wilson<float>(c->gcan, (const c64 *)U, (const c64 *)x + k0 * L, (c64 *)y + k0 * L, nullptr, m0, S, nk,
+                           W_QSHIFT, c->st);
+    }
+    return LQ_OK;
+  });
+}
+
+int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv, const lq_c128 *tv0,
+             const lq_mg_params *prm) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !agg || !tv0) fail(LQ_ERR_ARG, "mg_setup: NULL pointer");
+    int bvol = 1;
+    for (int m = 0; m < 4; ++m) {
+      if (agg[m] < 1 || c->L[m] % agg[m]) fail(LQ_ERR_ARG, "aggregate extent does not divide the lattice");
+      const int nb = c->L[m] / agg[m];
+      if (nb != 1 && nb % 2) fail(LQ_ERR_ARG, "need 1 or an even number of aggregates per direction");
+      bvol *= agg[m];
+    }
+    if (bvol > 256) fail(LQ_ERR_ARG, "aggregates hold at most 256 sites");
+    if (n_tv < 1 || n_tv > 32 || n_tv > 6 * bvol) fail(LQ_ERR_ARG, "need 1 <= n_tv <= min(32, 6*|aggregate|)");
+    lq_mg_params p;
+    lq_params_default(&p);
+    if (prm) p = *prm;
+    if (p.smoother != LQ_SMOOTH_SAP) fail(LQ_ERR_ARG, "only the SAP smoother is implemented on the device");
+    if (p.precision != LQ_PREC_FP64 && p.precision != LQ_PREC_MIXED) fail(LQ_ERR_ARG, "bad precision");
+    if (p.rqi_block < 1 || p.rqi_block > kMaxRhs) fail(LQ_ERR_ARG, "rqi_block must be in 1..16");
+    if (p.rqi_guard < 0) fail(LQ_ERR_ARG, "rqi_guard must be >= 0");
+    if (p.coarse_m < 1 || p.fgmres_m < 1 || p.sap_mr < 0 || p.post < 0 || p.pre < 0)
+      fail(LQ_ERR_ARG, "bad iteration parameters");
+    c->have = false;
+    c->p = p;
+    c->m0 = m0;
+    c->Nv = n_tv;
+    for (int m = 0; m < 4; ++m) c->agg[m] = agg[m];
+    c->g = make_geom(c->L, agg, c->tbc);
+    for (int m = 0; m < 4; ++m) c->cg.nb[m] = c->g.nb[m];
+    c->cg.nA = c->g.nblk;
+    c->cg.n2 = 2 * n_tv;
+    const long long V = c->g.V, V12 = 12LL * V;
+    // links
+    launch_pack_links<double>(c->g, (const c128 *)U, c->U64.get(36 * V), c->st);
+    if (p.precision == LQ_PREC_FP64) copy<double>(c, c->d64.U.get(36 * V), c->U64.p, 36 * V);
+    else launch_pack_links<float>(c->g, (const c128 *)U, c->d32.U.get(36 * V), c->st);
+    // red / black block lists
+    std::vector<int> lists[2];
+    for (int A = 0; A < c->g.nblk; ++A) {
+      int r = A, s = 0;
+      for (int m = 0; m < 3; ++m) { s += r % c->g.nb[m]; r /= c->g.nb[m]; }
+      s += r;
+      lists[s & 1].push_back(A);
+    }
+    for (int col = 0; col < 2; ++col) {
+      c->nblocks[col] = (int)lists[col].size();
+      int *d = c->blocks[col].get(std::max<size_t>(1, lists[col].size()));
+      if (!lists[col].empty())
+        LQ_HIP(hipMemcpyAsync(d, lists[col].data(), lists[col].size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+    }
+    // test vectors
+    c128 *W = c->W.get((size_t)n_tv * V12);
+    launch_permute<double>(c->g, (const c128 *)tv0, W, n_tv, true, c->st);
+    c128 *tmp = c->tmpA.get((size_t)kMaxRhs * V12);
+    std::vector<double> zs(kMaxRhs, 0.0);
+    for (int it = 0; it < p.n_init; ++it)
+      for (int k0 = 0; k0 < n_tv; k0 += kMaxRhs) {
+        const int nk = std::min(kMaxRhs, n_tv - k0);
+        smooth64(c, zs.data(), W + k0 * V12, tmp, nk, std::max(p.post, 1));
+        copy<double>(c, W + k0 * V12, tmp, (size_t)nk * V12);
+      }
+    orthonormalise(c, W, n_tv);
+    rebuild(c, W);
+    c->have = true;
+    for (int it = 0; it < p.n_setup; ++it) {
+      for (int k0 = 0; k0 < n_tv; k0 += kMaxRhs) {
+        const int nk = std::min(kMaxRhs, n_tv - k0);
+        precond64(c, zs.data(), W + k0 * V12, tmp, nk);
+        copy<double>(c, W + k0 * V12, tmp, (size_t)nk * V12);
+      }
+      orthonormalise(c, W, n_tv);
+      rebuild(c, W);
+    }
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+int mg_solve_shifted(lq_ctx *c, int n_rhs, const double *sigma, const lq_c128 *rhs, lq_c128 *x, double tol,
+                     lq_solve_stats *st) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n_rhs < 1 || n_rhs > kMaxRhs || !sigma || !rhs || !x || !(tol > 0))
+      fail(LQ_ERR_ARG, "mg_solve_shifted: bad arguments");
+    const long long V12 = 12LL * c->g.V;
+    c128 *b = c->tmpA.get((size_t)kMaxRhs * V12);
+    c128 *xb = c->tmpB.get((size_t)kMaxRhs * V12);
+    launch_permute<double>(c->g, (const c128 *)rhs, b, n_rhs, true, c->st);
+    int its[kMaxRhs];
+    double rr[kMaxRhs];
+    c->coarse_iters = 0;
+    bool ok = solve_shifted(c, n_rhs, sigma, b, xb, tol, its, rr);
+    launch_permute<double>(c->g, xb, (c128 *)x, n_rhs, false, c->st);
+    sync(c);
+    if (st) {
+      std::memset(st, 0, sizeof(*st));
+      for (int k = 0; k < n_rhs; ++k) { st->iters[k] = its[k]; st->relres[k] = rr[k]; }
+      st->coarse_iters = c->coarse_iters;
+    }
+    return ok ? LQ_OK : LQ_WARN_NOCONV;
+  });
+}
+
+int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout, double *resid, const lq_c128 *V0,
+                 int n_v0, lq_rqi_stats *stats) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n_eig < 1 || !(tol > 0) || !lambda || !Vout || !resid) fail(LQ_ERR_ARG, "rqi_lowmodes: bad arguments");
+    const int Nv = c->Nv;
+    const long long V12 = 12LL * c->g.V;
+    const int nw = n_eig + std::max(0, c->p.rqi_guard);        // working vectors
+    const int n_tv_used = std::min(Nv, nw);
+    if (n_v0 == nw) {
+      if (!V0) fail(LQ_ERR_ARG, "V0 is NULL");
+    } else if (n_v0 != nw - n_tv_used) {
+      fail(LQ_ERR_ARG, "n_v0 must be n_work - min(Nv, n_work) or n_work (n_work = n_eig + rqi_guard)");
+    } else if (n_v0 > 0 && !V0) {
+      fail(LQ_ERR_ARG, "V0 is NULL");
+    }
+    lq_rqi_stats S;
+    std::memset(&S, 0, sizeof(S));
+    c128 *E = c->eig.get((size_t)nw * V12);
+    if (n_v0 == nw) {
+      launch_permute<double>(c->g, (const c128 *)V0, E, nw, true, c->st);
+    } else {
+      copy<double>(c, E, c->W.p, (size_t)n_tv_used * V12);
+      if (n_v0 > 0) launch_permute<double>(c->g, (const c128 *)V0, E + n_tv_used * V12, n_v0, true, c->st);
+    }
+    orthonormalise(c, E, nw);
+    std::vector<double> lam(nw, 0.0), eps(nw, 1.0);
+    c128 *SEL = c->sel.get((size_t)Nv * V12);
+    auto rebuild_from = [&]() {
+      double t0 = now();
+      std::vector<int> idx;
+      if (nw <= Nv) {
+        for (int i = 0; i < nw; ++i) idx.push_back(i);
+      } else {
+        std::vector<int> o(nw);
+        for (int i = 0; i < nw; ++i) o[i] = i;
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return std::fabs(lam[a]) < std::fabs(lam[b]); });
+        idx.assign(o.begin(), o.begin() + Nv);
+        std::sort(idx.begin(), idx.end());
+      }
+      for (size_t q = 0; q < idx.size(); ++q) copy<double>(c, SEL + q * V12, E + idx[q] * V12, V12);
+      for (int q = (int)idx.size(); q < Nv; ++q) copy<double>(c, SEL + q * V12, c->W.p + q * V12, V12);
+      rebuild(c, SEL);
+      S.p_rebuilds++;
+      S.t_rebuild += now() - t0;
+    };
+    // the n_eig vectors with smallest |lambda| have converged
+    auto wanted_done = [&]() {
+      std::vector<int> o(nw);
+      for (int i = 0; i < nw; ++i) o[i] = i;
+      std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return std::fabs(lam[a]) < std::fabs(lam[b]); });
+      for (int q = 0; q < n_eig; ++q)
+        if (!(eps[o[q]] <= tol)) return false;
+      return true;
+    };
+    rebuild_from();
+    c128 *X = c->tmpB.get((size_t)kMaxRhs * V12);
+    c128 *B = c->tmpA.get((size_t)kMaxRhs * V12);
+    const int nb = c->p.rqi_block;
+    // lambda_i and eps_i = ||Q v_i - lambda_i v_i|| for the listed vectors
+    auto rq_resid = [&](const std::vector<int> &ids) {
+      for (size_t q0 = 0; q0 < ids.size(); q0 += kMaxRhs) {
+        const int nk = (int)std::min<size_t>(kMaxRhs, ids.size() - q0);
+        for (int q = 0; q < nk; ++q) copy<double>(c, B + q * V12, E + ids[q0 + q] * V12, V12);
+        Shifts z = shifts_of(nullptr, 0);
+        launch_wilson<double>(c->g, c->U64.p, B, X, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+        for (int q = 0; q < nk; ++q) {
+          const int i = ids[q0 + q];
+          auto d = dots<double>(c, 1, B + q * V12, 0, 0, X + q * V12, 0, V12, 1);
+          lam[i] = d[0].real();
+          axpys<double>(c, 1, B + q * V12, 0, 0, std::vector<cd>{cd(lam[i])}, X + q * V12, 0, V12, 1, -1.0);
+          eps[i] = norms<double>(c, X + q * V12, V12, 1)[0];
+        }
+      }
+    };
+    bool done = false;
+    while (!done && S.sweeps < c->p.rqi_max_sweeps) {
+      std::vector<int> todo;
+      for (int i = 0; i < nw; ++i)
+        if (eps[i] > tol) todo.push_back(i);
+      if (todo.empty()) break;
+      for (size_t q0 = 0; q0 < todo.size(); q0 += nb) {
+        const int nk = (int)std::min<size_t>(nb, todo.size() - q0);
+        std::vector<double> sig(nk);
+        for (int q = 0; q < nk; ++q) {
+          const int i = todo[q0 + q];
+          sig[q] = lam[i] * std::max(1.0 - eps[i], 0.0);        // damped shift (Alg. 1)
+          copy<double>(c, B + q * V12, E + i * V12, V12);
+        }
+        double t0 = now();
+        int its[kMaxRhs];
+        double rr[kMaxRhs];
+        solve_shifted(c, nk, sig.data(), B, X, c->p.rqi_solve_tol, its, rr);
+        for (int q = 0; q < nk; ++q) S.fgmres_iters += its[q];
+        S.solves += nk;
+        S.t_solve += now() - t0;
+        t0 = now();
+        for (int q = 0; q < nk; ++q) {
+          const int i = todo[q0 + q];
+          c128 *x = X + q * V12;
+          for (int pass = 0; pass < 2; ++pass) {
+            auto h = dots<double>(c, i, E, V12, 0, x, 0, V12, 1);
+            axpys<double>(c, i, E, V12, 0, h, x, 0, V12, 1, -1.0);
+          }
+          auto nr = norms<double>(c, x, V12, 1);
+          if (!(nr[0] > 0) || !std::isfinite(nr[0])) fail(LQ_ERR_NUMERIC, "RQI iterate collapsed");
+          scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, x, 0, E + i * V12, 0, V12, 1, false);
+        }
+        S.t_ortho += now() - t0;
+        rebuild_from();
+        t0 = now();
+        rq_resid(std::vector<int>(todo.begin() + q0, todo.begin() + q0 + nk));
+        S.t_rq += now() - t0;
+      }
+      S.sweeps++;
+      if (c->p.rayleigh_ritz && nw > 1) {
+        double t0 = now();
+        rayleigh_ritz(c, E, nw, lam);
+        std::vector<int> all(nw);
+        for (int i = 0; i < nw; ++i) all[i] = i;
+        rq_resid(all);
+        S.t_rq += now() - t0;
+        rebuild_from();
+      }
+      done = wanted_done();
+    }
+    // output: the n_eig smallest |lambda|, sorted by (|lambda|, lambda)
+    std::vector<int> o(nw);
+    for (int i = 0; i < nw; ++i) o[i] = i;
+    std::sort(o.begin(), o.end(), [&](int a, int b) {
+      if (std::fabs(lam[a]) != std::fabs(lam[b])) return std::fabs(lam[a]) < std::fabs(lam[b]);
+      return lam[a] < lam[b];
+    });
+    for (int q = 0; q < n_eig; ++q) {
+      lambda[q] = lam[o[q]];
+      resid[q] = eps[o[q]];
+      launch_permute<double>(c->g, E + o[q] * V12, (c128 *)Vout + q * V12, 1, false, c->st);
+    }
+    sync(c);
+    if (stats) *stats = S;
+    return done ? LQ_OK : LQ_WARN_NOCONV;
+  });
+}
+
+int mg_info(lq_ctx *c, int *nv, int *n_agg) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (nv) *nv = c->Nv;
+    if (n_agg) *n_agg = c->cg.nA;
+    return LQ_OK;
+  });
+}
+
+int mg_get_interp(lq_ctx *c, lq_c128 *P) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (!P) fail(LQ_ERR_ARG, "NULL");
+    launch_permute<double>(c->g, c->P64.p, (c128 *)P, c->Nv, false, c->st);
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+int mg_get_coarse(lq_ctx *c, lq_c128 *Qc) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (!Qc) fail(LQ_ERR_ARG, "NULL");
+    const size_t n = (size_t)c->cg.nA * 5 * c->cg.n2 * c->cg.n2;
+    if (c->p.precision == LQ_PREC_FP64) copy<double>(c, (c128 *)Qc, c->d64.Qc.p, n);
+    else launch_convert<double, float>(c->d32.Qc.p, (c128 *)Qc, (long long)n, c->st);
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+// Component entry points run in the hierarchy's precision with FP64 interfaces.
+int mg_restrict(lq_ctx *c, int n, const lq_c128 *f, lq_c128 *out) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n < 1 || n > kMaxRhs || !f || !out) fail(LQ_ERR_ARG, "bad arguments");
+    const long long V12 = 12LL * c->g.V, nc = (long long)c->cg.nA * c->cg.n2;
+    c128 *fb = c->tmpA.get((size_t)kMaxRhs * V12);
+    launch_permute<double>(c->g, (const c128 *)f, fb, n, true, c->st);
+    if (c->p.precision == LQ_PREC_FP64) {
+      launch_restrict<double>(c->g, c->d64.P.p, c->Nv, fb, V12, n, (c128 *)out, c->st);
+    } else {
+      c64 *f32 = c->f32a.get((size_t)n * V12);
+      c64 *o32 = c->c32b.get((size_t)n * nc);
+      launch_convert<float, double>(fb, f32, n * V12, c->st);
+      launch_restrict<float>(c->g, c->d32.P.p, c->Nv, f32, V12, n, o32, c->st);
+      launch_convert<double, float>(o32, (c128 *)out, n * nc, c->st);
+    }
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+int mg_prolong(lq_ctx *c, int n, const lq_c128 *cin, lq_c128 *f) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n < 1 || n > kMaxRhs || !cin || !f) fail(LQ_ERR_ARG, "bad arguments");
+    const long long V12 = 12LL * c->g.V, nc = (long long)c->cg.nA * c->cg.n2;
+    c128 *fb = c->tmpA.get((size_t)kMaxRhs * V12);
+    if (c->p.precision == LQ_PREC_FP64) {
+      launch_prolong<double>(c->g, c->d64.P.p, c->Nv, (const c128 *)cin, fb, V12, n, false, c->st);
+    } else {
+      c64 *c32 = c->c32b.get((size_t)n * nc);
+      c64 *f32 = c->f32a.get((size_t)n * V12);
+      launch_convert<float, double>((const c128 *)cin, c32, n * nc, c->st);
+      launch_prolong<float>(c->g, c->d32.P.p, c->Nv, c32, f32, V12, n, false, c->st);
+      launch_convert<double, float>(f32, fb, n * V12, c->st);
+    }
+    launch_permute<double>(c->g, fb, (c128 *)f, n, false, c->st);
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+int mg_coarse_apply(lq_ctx *c, int n, const double *sigma, const lq_c128 *x, lq_c128 *y) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n < 1 || n > kMaxRhs || !sigma || !x || !y) fail(LQ_ERR_ARG, "bad arguments");
+    const long long nc = (long long)c->cg.nA * c->cg.n2;
+    Shifts S = shifts_of(sigma, n);
+    if (c->p.precision == LQ_PREC_FP64) {
+      launch_coarse_apply<double>(c->cg, c->d64.Qc.p, (const c128 *)x, (c128 *)y, S, n, false, c->st);
+    } else {
+      c64 *a = c->c32b.get((size_t)2 * n * nc);
+      launch_convert<float, double>((const c128 *)x, a, n * nc, c->st);
+      launch_coarse_apply<float>(c->cg, c->d32.Qc.p, a, a + n * nc, S, n, false, c->st);
+      launch_convert<double, float>(a + n * nc, (c128 *)y, n * nc, c->st);
+    }
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+int mg_smooth(lq_ctx *c, int n, const double *sigma, const lq_c128 *r, lq_c128 *z, int steps) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n < 1 || n > kMaxRhs || !sigma || !r || !z || steps < 0) fail(LQ_ERR_ARG, "bad arguments");
+    const long long V12 = 12LL * c->g.V;
+    c128 *rb = c->tmpA.get((size_t)kMaxRhs * V12), *zb = c->tmpB.get((size_t)kMaxRhs * V12);
+    launch_permute<double>(c->g, (const c128 *)r, rb, n, true, c->st);
+    smooth64(c, sigma, rb, zb, n, steps);
+    launch_permute<double>(c->g, zb, (c128 *)z, n, false, c->st);
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+int mg_cycle(lq_ctx *c, int n, const double *sigma, const lq_c128 *r, lq_c128 *z) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (n < 1 || n > kMaxRhs || !sigma || !r || !z) fail(LQ_ERR_ARG, "bad arguments");
+    const long long V12 = 12LL * c->g.V;
+    c128 *rb = c->tmpA.get((size_t)kMaxRhs * V12), *zb = c->tmpB.get((size_t)kMaxRhs * V12);
+    launch_permute<double>(c->g, (const c128 *)r, rb, n, true, c->st);
+    precond64(c, sigma, rb, zb, n);
+    launch_permute<double>(c->g, zb, (c128 *)z, n, false, c->st);
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+}  // extern "C"

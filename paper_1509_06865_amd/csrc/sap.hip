@@ -1,0 +1,155 @@
+// Schwarz alternating procedure (SAP) smoother, one colour pass per launch.
+//
+// SAP is applied to D_sigma = gamma5 (Q - sigma) = D - sigma gamma5 with
+// right-hand side gamma5 r, which with exact block solves gives the same
+// iterates as SAP on Q - sigma (gamma5 is site-local), while its block
+// systems are well suited to minimal-residual steps.  One workgroup owns one
+// block (the lattice is stored blocked, so the block's sites are contiguous):
+// it forms the block residual with the full stencil, runs the MR steps on the
+// Dirichlet block operator with the iterate exchanged through LDS, and adds
+// the correction to z.  Blocks of one colour never touch each other.
+#include "lq_kernels.h"
+#include "lq_dslash.h"
+
+namespace lq {
+namespace {
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of three doubles over the workgroup, broadcast to all threads.
+__device__ inline void block_sum3(double &a, double &b, double &c, double *lds) {
+  a = wsum(a); b = wsum(b); c = wsum(c);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) { lds[3 * wave] = a; lds[3 * wave + 1] = b; lds[3 * wave + 2] = c; }
+  __syncthreads();
+  a = b = c = 0;
+  for (int w = 0; w < nw; ++w) { a += lds[3 * w]; b += lds[3 * w + 1]; c += lds[3 * w + 2]; }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__restrict__ U,
+                                                    const cplx<T> *__restrict__ rin, cplx<T> *__restrict__ zio,
+                                                    const int *__restrict__ blocks, T m0, Shifts sig, int n_mr) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);          // [12][bvol]
+  __shared__ double red[3 * 16];
+  const int B = blocks[blockIdx.x];
+  const int k = blockIdx.y;
+  const int t = threadIdx.x;
+  const bool active = t < g.bvol;
+  const int s = B * g.bvol + (active ? t : 0);
+  const long long off = (long long)k * 12 * g.V;
+  const cplx<T> *r = rin + off;
+  cplx<T> *z = zio + off;
+  const T sgm = (T)sig.s[k];
+  const T diag = (T)4 + m0;
+  SiteCoord c = decode(g, s);
+
+  // block residual rho = gamma5 r - D_sigma z (full stencil)
+  cplx<T> rho[12], e[12], p[12], q[12];
+  if (active) {
+    cplx<T> acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      float sg; bool in;
+      int sf = neighbour(g, s, c, mu, true, &sg, &in);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) q[i] = z[(long long)i * g.V + sf];
+      hop(mu, true, q, U, g.V, s, (T)sg, acc);
+      int sb = neighbour(g, s, c, mu, false, &sg, &in);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) q[i] = z[(long long)i * g.V + sb];
+      hop(mu, false, q, U, g.V, sb, (T)sg, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const cplx<T> zi = z[(long long)i * g.V + s];
+      const cplx<T> ri = r[(long long)i * g.V + s];
+      const T g5 = (i < 6) ? (T)1 : (T)-1;
+      // D_sigma z = (4+m0) z - acc/2 - sigma gamma5 z
+      const cplx<T> dz = diag * zi - (T)0.5 * acc[i] - (sgm * g5) * zi;
+      rho[i] = g5 * ri - dz;
+      e[i] = mk<T>(0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) { rho[i] = mk<T>(0, 0); e[i] = mk<T>(0, 0); }
+  }
+
+  for (int it = 0; it < n_mr; ++it) {
+    __syncthreads();
+    if (active)
+#pragma unroll
+      for (int i = 0; i < 12; ++i) lds[i * g.bvol + t] = rho[i];
+    __syncthreads();
+    double num_re = 0, num_im = 0, den = 0;
+    if (active) {
+      cplx<T> acc[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        if (c.l[mu] + 1 < g.b[mu]) {
+          const int tn = t + g.sl[mu];
+#pragma unroll
+          for (int i = 0; i < 12; ++i) q[i] = lds[i * g.bvol + tn];
+          hop(mu, true, q, U, g.V, s, (T)1, acc);
+        }
+        if (c.l[mu] > 0) {
+          const int tn = t - g.sl[mu];
+#pragma unroll
+          for (int i = 0; i < 12; ++i) q[i] = lds[i * g.bvol + tn];
+          hop(mu, false, q, U, g.V, s - g.sl[mu], (T)1, acc);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        const T g5 = (i < 6) ? (T)1 : (T)-1;
+        p[i] = diag * rho[i] - (T)0.5 * acc[i] - (sgm * g5) * rho[i];
+        // <p, rho> and <p, p>
+        num_re += (double)p[i].re * rho[i].re + (double)p[i].im * rho[i].im;
+        num_im += (double)p[i].re * rho[i].im - (double)p[i].im * rho[i].re;
+        den += (double)p[i].re * p[i].re + (double)p[i].im * p[i].im;
+      }
+    }
+    block_sum3(num_re, num_im, den, red);
+    cplx<T> alpha = mk<T>(0, 0);
+    if (den > 0) alpha = mk<T>((T)(num_re / den), (T)(num_im / den));
+    if (active)
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        e[i] = e[i] + alpha * rho[i];
+        rho[i] = rho[i] - alpha * p[i];
+      }
+  }
+  __syncthreads();
+  if (active)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) z[(long long)i * g.V + s] = z[(long long)i * g.V + s] + e[i];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T> *z, const int *blocks,
+                       int nblocks, double m0, const Shifts &sig, int nrhs, int n_mr, hipStream_t st) {
+  const int threads = ((g.bvol + 63) / 64) * 64;
+  const size_t lds = (size_t)12 * g.bvol * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_sap_colour<T>), dim3(nblocks, nrhs), dim3(threads), lds, st, g, U, r, z, blocks, (T)m0,
+                     sig, n_mr);
+  LQ_HIP(hipGetLastError());
+}
+
+template void launch_sap_colour<float>(const Geom &, const c64 *, const c64 *, c64 *, const int *, int, double,
+                                       const Shifts &, int, int, hipStream_t);
+template void launch_sap_colour<double>(const Geom &, const c128 *, const c128 *, c128 *, const int *, int,
+                                        double, const Shifts &, int, int, hipStream_t);
+
+}  // namespace lq

@@ -1,0 +1,231 @@
+// Grid transfers of the aggregation multigrid (sec. 2): the gamma5-split
+// interpolation P = diag(P1, P2), restriction R = P^dag, prolongation, the
+// local orthonormalisation that builds P from test vectors, and the scatter of
+// restricted split hops into the Galerkin operator Q_c = P^dag Q P.
+//
+// The fine lattice is stored blocked by aggregate, so one workgroup owns the
+// contiguous sites of one aggregate; P is stored as Nv fields in the same
+// layout, its restriction to (aggregate, gamma5 half) being one column.
+#include "lq_kernels.h"
+
+namespace lq {
+namespace {
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// c[j][A][h*Nv + k] = sum over the aggregate's sites of conj(P_k) . f_j on half h
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict(Geom g, const cplx<T> *__restrict__ P, int Nv,
+                                                  const cplx<T> *__restrict__ f, long long fstride,
+                                                  cplx<T> *__restrict__ c) {
+  __shared__ double part[4][64][4];     // [wave][k][h re, h im]
+  const int A = blockIdx.x, j = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  const bool active = t < g.bvol;
+  const int s = A * g.bvol + (active ? t : 0);
+  cplx<T> fv[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) fv[i] = active ? f[j * fstride + (long long)i * g.V + s] : mk<T>(0, 0);
+  for (int k = 0; k < Nv; ++k) {
+    double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+    if (active) {
+      const cplx<T> *Pk = P + (long long)k * 12 * g.V;
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        const cplx<T> pv = Pk[(long long)i * g.V + s];
+        const double re = (double)pv.re * fv[i].re + (double)pv.im * fv[i].im;
+        const double im = (double)pv.re * fv[i].im - (double)pv.im * fv[i].re;
+        if (i < 6) { a0r += re; a0i += im; } else { a1r += re; a1i += im; }
+      }
+    }
+    a0r = wsum(a0r); a0i = wsum(a0i); a1r = wsum(a1r); a1i = wsum(a1i);
+    if (lane == 0) { part[wave][k][0] = a0r; part[wave][k][1] = a0i; part[wave][k][2] = a1r; part[wave][k][3] = a1i; }
+  }
+  __syncthreads();
+  const int n2 = 2 * Nv;
+  if (t < n2) {
+    const int h = t / Nv, k = t - h * Nv;
+    double re = 0, im = 0;
+    for (int w = 0; w < nw; ++w) { re += part[w][k][2 * h]; im += part[w][k][2 * h + 1]; }
+    c[((long long)j * g.nblk + A) * n2 + t] = mk<T>((T)re, (T)im);
+  }
+}
+
+// f_j(x) (+)= sum_k P_k(x) c_j[A][h(x) Nv + k]
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong(Geom g, const cplx<T> *__restrict__ P, int Nv,
+                                                 const cplx<T> *__restrict__ c, cplx<T> *__restrict__ f,
+                                                 long long fstride, bool acc) {
+  __shared__ cplx<T> cs[64];
+  const int A = blockIdx.x, j = blockIdx.y;
+  const int t = threadIdx.x;
+  const int n2 = 2 * Nv;
+  if (t < n2) cs[t] = c[((long long)j * g.nblk + A) * n2 + t];
+  __syncthreads();
+  if (t >= g.bvol) return;
+  const int s = A * g.bvol + t;
+  cplx<T> out[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) out[i] = mk<T>(0, 0);
+  for (int k = 0; k < Nv; ++k) {
+    const cplx<T> *Pk = P + (long long)k * 12 * g.V;
+    const cplx<T> c0 = cs[k], c1 = cs[Nv + k];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) out[i] = out[i] + Pk[(long long)i * g.V + s] * (i < 6 ? c0 : c1);
+  }
+  cplx<T> *fj = f + j * fstride;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const long long e = (long long)i * g.V + s;
+    fj[e] = acc ? fj[e] + out[i] : out[i];
+  }
+}
+
+// Cholesky-QR, applied twice, of the (6*bvol) x Nv local matrix of aggregate
+// A and gamma5 half h.  Gram G = W^dag W, G = L L^dag, P = W L^-dag; the QR
+// factor with positive diagonal is unique, so this is the same orthonormal
+// basis that Gram-Schmidt in vector order produces.
+constexpr int kMaxNv = 32;
+__global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict__ W, int Nv,
+                                                 c128 *__restrict__ P, int *status) {
+  __shared__ double part[4][kMaxNv * (kMaxNv + 1) / 2 * 2];   // wave partial sums of the Gram entries
+  __shared__ c128 L[kMaxNv][kMaxNv];
+  __shared__ int bad;
+  const int A = blockIdx.x, h = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  const bool active = t < g.bvol;
+  const int s = A * g.bvol + (active ? t : 0);
+  const int npair = Nv * (Nv + 1) / 2;
+  if (t == 0) bad = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const c128 *src = (pass == 0) ? W : P;
+    // Gram partials, pairs (i <= j) in row-major order
+    int pidx = 0;
+    for (int i = 0; i < Nv; ++i) {
+      c128 wi[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+        wi[r] = active ? src[((long long)i * 12 + 6 * h + r) * g.V + s] : c128{0, 0};
+      for (int jj = i; jj < Nv; ++jj, ++pidx) {
+        double re = 0, im = 0;
+        if (active) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            const c128 wj = src[((long long)jj * 12 + 6 * h + r) * g.V + s];
+            re += wi[r].re * wj.re + wi[r].im * wj.im;
+            im += wi[r].re * wj.im - wi[r].im * wj.re;
+          }
+        }
+        re = wsum(re); im = wsum(im);
+        if (lane == 0) { part[wave][2 * pidx] = re; part[wave][2 * pidx + 1] = im; }
+      }
+    }
+    __syncthreads();
+    // Gram matrix into L (upper part, then Cholesky in place by thread 0)
+    for (int q = t; q < npair; q += blockDim.x) {
+      int i = 0, rem = q;
+      while (rem >= Nv - i) { rem -= Nv - i; ++i; }
+      const int jj = i + rem;
+      double re = 0, im = 0;
+      for (int w = 0; w < nw; ++w) { re += part[w][2 * q]; im += part[w][2 * q + 1]; }
+      L[jj][i] = c128{re, -im};       // G[j][i] = conj(G[i][j]), lower triangle
+    }
+    __syncthreads();
+    if (t == 0) {
+      // G = L L^dag:  L[i][j] = (G[i][j] - sum_{k<j} L[i][k] conj(L[j][k])) / L[j][j]
+      for (int jj = 0; jj < Nv; ++jj) {
+        const double gjj = L[jj][jj].re;
+        double d = gjj;
+        for (int k = 0; k < jj; ++k) d -= norm2(L[jj][k]);
+        if (!(d > 1e-13 * gjj) || !(gjj > 0)) { bad = 1; d = 1.0; }
+        const double ljj = sqrt(d);
+        L[jj][jj] = c128{ljj, 0};
+        for (int i = jj + 1; i < Nv; ++i) {
+          c128 v = L[i][jj];
+          for (int k = 0; k < jj; ++k) v = v - cmul_conj(L[jj][k], L[i][k]);
+          L[i][jj] = (1.0 / ljj) * v;
+        }
+      }
+    }
+    __syncthreads();
+    // P rows: p = w L^-dag  <=>  sum_{i<=j} p_i conj(L[j][i]) = w_j
+    if (active) {
+      for (int r = 0; r < 6; ++r) {
+        c128 pr[kMaxNv];
+        for (int jj = 0; jj < Nv; ++jj) {
+          c128 v = src[((long long)jj * 12 + 6 * h + r) * g.V + s];
+          for (int i = 0; i < jj; ++i) v = v - pr[i] * conj(L[jj][i]);
+          pr[jj] = (1.0 / L[jj][jj].re) * v;
+        }
+        for (int jj = 0; jj < Nv; ++jj) P[((long long)jj * 12 + 6 * h + r) * g.V + s] = pr[jj];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0 && bad) atomicOr(status, 1);
+}
+
+template <typename T>
+__global__ void k_scatter_coarse(const cplx<T> *__restrict__ pc, int nf, const int *__restrict__ cols, int n2,
+                                 int nA, cplx<T> *__restrict__ Qc) {
+  // pc[j][d][A][row] -> Qc[A][d][row][cols[j]]
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)nf * 5 * nA * n2;
+  if (e >= tot) return;
+  const int row = (int)(e % n2);
+  long long r = e / n2;
+  const int A = (int)(r % nA); r /= nA;
+  const int d = (int)(r % 5);
+  const int j = (int)(r / 5);
+  Qc[(((long long)A * 5 + d) * n2 + row) * n2 + cols[j]] = pc[e];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_restrict(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *f, long long fstride, int nf,
+                     cplx<T> *c, hipStream_t st) {
+  const int threads = ((g.bvol + 63) / 64) * 64;
+  hipLaunchKernelGGL((k_restrict<T>), dim3(g.nblk, nf), dim3(threads), 0, st, g, P, Nv, f, fstride, c);
+  LQ_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_prolong(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *c, cplx<T> *f, long long fstride,
+                    int nf, bool accumulate, hipStream_t st) {
+  const int threads = ((g.bvol + 63) / 64) * 64;
+  hipLaunchKernelGGL((k_prolong<T>), dim3(g.nblk, nf), dim3(threads), 0, st, g, P, Nv, c, f, fstride,
+                     accumulate);
+  LQ_HIP(hipGetLastError());
+}
+
+void launch_build_P(const Geom &g, const c128 *W, int Nv, c128 *P64, int *status, hipStream_t st) {
+  const int threads = ((g.bvol + 63) / 64) * 64;
+  hipLaunchKernelGGL(k_build_P, dim3(g.nblk, 2), dim3(threads), 0, st, g, W, Nv, P64, status);
+  LQ_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_scatter_coarse(const cplx<T> *parts_c, int nf, const int *cols_dev, int n2, int nA, cplx<T> *Qc,
+                           hipStream_t st) {
+  const long long tot = (long long)nf * 5 * nA * n2;
+  hipLaunchKernelGGL((k_scatter_coarse<T>), dim3(blocks_for(tot, 256)), dim3(256), 0, st, parts_c, nf, cols_dev,
+                     n2, nA, Qc);
+  LQ_HIP(hipGetLastError());
+}
+
+#define LQ_INST(T)                                                                                           \
+  template void launch_restrict<T>(const Geom &, const cplx<T> *, int, const cplx<T> *, long long, int,      \
+                                   cplx<T> *, hipStream_t);                                                 \
+  template void launch_prolong<T>(const Geom &, const cplx<T> *, int, const cplx<T> *, cplx<T> *, long long, \
+                                  int, bool, hipStream_t);                                                  \
+  template void launch_scatter_coarse<T>(const cplx<T> *, int, const int *, int, int, cplx<T> *, hipStream_t);
+LQ_INST(float)
+LQ_INST(double)
+#undef LQ_INST
+
+}  // namespace lq

@@ -1,0 +1,135 @@
+// Wilson-Dirac stencil for Q = gamma5 D (sec. 2), one thread per lattice site.
+//
+// Each hop is applied in spin-projected form (lq_dslash.h): only the two-spin
+// upper half of (1 -+ gamma_mu) psi is multiplied by the link.
+#include "lq_kernels.h"
+#include "lq_dslash.h"
+
+namespace lq {
+namespace {
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restrict__ U,
+                                                const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
+                                                const cplx<T> *__restrict__ bin, T m0, Shifts sig) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int k = blockIdx.y;
+  const long long off = (long long)k * 12 * g.V;
+  const cplx<T> *x = xin + off;
+  const SiteCoord c = decode(g, s);
+  cplx<T> acc[12], p[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+  // a rolled loop over directions bounds the live ranges (one hop pair at a time)
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    float sg;
+    bool in;
+    const int sf = neighbour(g, s, c, mu, true, &sg, &in);
+    load_spinor(x, g.V, sf, p);
+    hop(mu, true, p, U, g.V, s, (T)sg, acc);
+    const int sb = neighbour(g, s, c, mu, false, &sg, &in);
+    load_spinor(x, g.V, sb, p);
+    hop(mu, false, p, U, g.V, sb, (T)sg, acc);
+  }
+  load_spinor(x, g.V, s, p);
+  const T diag = (T)4 + m0;
+  const T sgm = (T)sig.s[k];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    cplx<T> d = diag * p[i] - (T)0.5 * acc[i];
+    if (i >= 6) d = -d;                        // gamma5
+    d = d - sgm * p[i];
+    if (MODE == W_RESID) d = bin[off + (long long)i * g.V + s] - d;
+    yout[off + (long long)i * g.V + s] = d;
+  }
+}
+
+// Parts of Q for the Galerkin product, per column field j.
+template <typename T>
+__global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__restrict__ U,
+                                                      const cplx<T> *__restrict__ xin, long long xstride,
+                                                      cplx<T> *__restrict__ parts, T m0, const int *half_dev) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int j = blockIdx.y;
+  const int half = half_dev[j];
+  const cplx<T> *x = xin + (long long)j * xstride;
+  cplx<T> *out = parts + (long long)j * 5 * 12 * g.V;
+  const SiteCoord c = decode(g, s);
+  // x with the unused gamma5 half read as zero
+  auto ld = [&](int site, cplx<T> p[12]) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const bool use = (half == 0) ? (i < 6) : (i >= 6);
+      p[i] = use ? x[(long long)i * g.V + site] : mk<T>(0, 0);
+    }
+  };
+  cplx<T> self[12], cross[12], p[12];
+  ld(s, p);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) self[i] = ((T)4 + m0) * p[i];
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    float sg;
+    bool in;
+    const int sf = neighbour(g, s, c, mu, true, &sg, &in);
+    ld(sf, p);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) cross[i] = mk<T>(0, 0);
+    hop(mu, true, p, U, g.V, s, (T)sg, cross);
+    if (in) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) { self[i] = self[i] - (T)0.5 * cross[i]; cross[i] = mk<T>(0, 0); }
+    }
+    // crossing part, -1/2 and gamma5 applied
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      out[(long long)((1 + mu) * 12 + i) * g.V + s] = (i >= 6 ? (T)0.5 : (T)-0.5) * cross[i];
+    const int sb = neighbour(g, s, c, mu, false, &sg, &in);
+    if (in) {
+      ld(sb, p);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) cross[i] = mk<T>(0, 0);
+      hop(mu, false, p, U, g.V, sb, (T)sg, cross);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) self[i] = self[i] - (T)0.5 * cross[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) out[(long long)i * g.V + s] = (i >= 6) ? -self[i] : self[i];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y, const cplx<T> *b,
+                   double m0, const Shifts &sig, int nrhs, int mode, hipStream_t st) {
+  dim3 grid(blocks_for(g.V, 256), nrhs);
+  if (mode == W_QSHIFT)
+    hipLaunchKernelGGL((k_wilson<T, W_QSHIFT>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig);
+  else
+    hipLaunchKernelGGL((k_wilson<T, W_RESID>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig);
+  LQ_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_coarse_parts(const Geom &g, const cplx<T> *U, const cplx<T> *x, const int *half_dev,
+                         int nf, long long xstride, cplx<T> *parts, double m0, hipStream_t st) {
+  dim3 grid(blocks_for(g.V, 256), nf);
+  hipLaunchKernelGGL((k_coarse_parts<T>), grid, dim3(256), 0, st, g, U, x, xstride, parts, (T)m0,
+                     half_dev);
+  LQ_HIP(hipGetLastError());
+}
+
+template void launch_wilson<float>(const Geom &, const c64 *, const c64 *, c64 *, const c64 *, double,
+                                   const Shifts &, int, int, hipStream_t);
+template void launch_wilson<double>(const Geom &, const c128 *, const c128 *, c128 *, const c128 *, double,
+                                    const Shifts &, int, int, hipStream_t);
+template void launch_coarse_parts<float>(const Geom &, const c64 *, const c64 *, const int *, int, long long,
+                                         c64 *, double, hipStream_t);
+template void launch_coarse_parts<double>(const Geom &, const c128 *, const c128 *, const int *, int,
+                                          long long, c128 *, double, hipStream_t);
+
+}  // namespace lq

@@ -1,0 +1,251 @@
+"""ctypes binding of liblqmg (include/lqmg.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device memory comes from torch tensors on the current HIP device;
+the context issues its work on the stream given at creation (default: torch's
+current stream).  The library must be built (``paper_1509_06865_amd.build``);
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "liblqmg.so")
+_lib = None
+
+LQ_OK, LQ_WARN_NOCONV = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+SMOOTH_SAP, SMOOTH_GMRES = 0, 1
+EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
+            "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
+            "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle"]
+
+
+class LQError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblqmg error {code}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("precision", C.c_int), ("smoother", C.c_int), ("pre", C.c_int), ("post", C.c_int),
+                ("sap_mr", C.c_int), ("gmres_smooth_m", C.c_int), ("coarse_m", C.c_int),
+                ("coarse_restarts", C.c_int), ("coarse_tol", C.c_double), ("fgmres_m", C.c_int),
+                ("fgmres_restarts", C.c_int), ("n_init", C.c_int), ("n_setup", C.c_int),
+                ("rqi_block", C.c_int), ("rqi_max_sweeps", C.c_int), ("rqi_solve_tol", C.c_double),
+                ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int)]
+
+
+class _SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int * 16), ("relres", C.c_double * 16), ("coarse_iters", C.c_int)]
+
+
+class _RQIStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int), ("solves", C.c_int), ("fgmres_iters", C.c_int), ("p_rebuilds", C.c_int),
+                ("t_solve", C.c_double), ("t_ortho", C.c_double), ("t_rebuild", C.c_double),
+                ("t_rq", C.c_double)]
+
+
+@dataclass
+class MGParams:
+    """Mirror of lq_mg_params; None fields keep the library default."""
+    precision: int | None = None
+    smoother: int | None = None
+    pre: int | None = None
+    post: int | None = None
+    sap_mr: int | None = None
+    gmres_smooth_m: int | None = None
+    coarse_m: int | None = None
+    coarse_restarts: int | None = None
+    coarse_tol: float | None = None
+    fgmres_m: int | None = None
+    fgmres_restarts: int | None = None
+    n_init: int | None = None
+    n_setup: int | None = None
+    rqi_block: int | None = None
+    rqi_max_sweeps: int | None = None
+    rqi_solve_tol: float | None = None
+    rayleigh_ritz: int | None = None
+    rqi_guard: int | None = None
+
+    def to_c(self, lib) -> _Params:
+        p = _Params()
+        lib.lq_params_default(C.byref(p))
+        for f in fields(self):
+            v = getattr(self, f.name)
+            if v is not None:
+                setattr(p, f.name, v)
+        return p
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load liblqmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: run `python -m paper_1509_06865_amd.build` first")
+    lib = C.CDLL(_LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    ip, dp = C.POINTER(C.c_int), C.POINTER(C.c_double)
+    sig = {
+        "lq_params_default": (i, [C.POINTER(_Params)]),
+        "lq_create": (i, [C.POINTER(vp), ip, i, vp]),
+        "lq_destroy": (i, [vp]),
+        "lq_last_error": (C.c_char_p, [vp]),
+        "q_apply": (i, [vp, vp, d, vp, vp, i]),
+        "q_apply_c64": (i, [vp, vp, d, vp, vp, i]),
+        "mg_setup": (i, [vp, vp, d, ip, i, vp, C.POINTER(_Params)]),
+        "mg_solve_shifted": (i, [vp, i, dp, vp, vp, d, C.POINTER(_SolveStats)]),
+        "rqi_lowmodes": (i, [vp, i, d, dp, vp, dp, vp, i, C.POINTER(_RQIStats)]),
+        "mg_info": (i, [vp, ip, ip]),
+        "mg_get_interp": (i, [vp, vp]),
+        "mg_get_coarse": (i, [vp, vp]),
+        "mg_restrict": (i, [vp, i, vp, vp]),
+        "mg_prolong": (i, [vp, i, vp, vp]),
+        "mg_coarse_apply": (i, [vp, i, dp, vp, vp]),
+        "mg_smooth": (i, [vp, i, dp, vp, vp, i]),
+        "mg_cycle": (i, [vp, i, dp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dbl(vals):
+    arr = (C.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+class Context:
+    """One lattice (dims = (X, Y, Z, T), t_bc = -1 antiperiodic / +1 periodic)."""
+
+    def __init__(self, dims, t_bc: int = -1, stream: torch.cuda.Stream | None = None):
+        self.lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        dims_c = (C.c_int * 4)(*self.dims)
+        rc = self.lib.lq_create(C.byref(h), dims_c, int(t_bc), C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise LQError(rc, "lq_create failed")
+        self.h = h
+        self.nv = None
+        self.n_agg = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_warn=False):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise LQError(rc, self.lib.lq_last_error(self.h).decode())
+        return rc
+
+    # -- Q ----------------------------------------------------------------------
+    def q_apply(self, U: torch.Tensor, m0: float, x: torch.Tensor, out: torch.Tensor | None = None):
+        n = x.shape[0] if x.dim() == 3 else 1
+        y = torch.empty_like(x) if out is None else out
+        if x.dtype == torch.complex128:
+            self._check(self.lib.q_apply(self.h, _ptr(U), float(m0), _ptr(x), _ptr(y), n))
+        elif x.dtype == torch.complex64:
+            self._check(self.lib.q_apply_c64(self.h, _ptr(U), float(m0), _ptr(x), _ptr(y), n))
+        else:
+            raise TypeError("x must be complex64 or complex128")
+        return y
+
+    # -- multigrid ------------------------------------------------------------------
+    def mg_setup(self, U, m0, agg, tv0, params: MGParams | None = None):
+        p = (params or MGParams()).to_c(self.lib)
+        agg_c = (C.c_int * 4)(*[int(a) for a in agg])
+        self._check(self.lib.mg_setup(self.h, _ptr(U), float(m0), agg_c, int(tv0.shape[0]), _ptr(tv0),
+                                      C.byref(p)))
+        nv, na = C.c_int(), C.c_int()
+        self._check(self.lib.mg_info(self.h, C.byref(nv), C.byref(na)))
+        self.nv, self.n_agg = nv.value, na.value
+
+    def mg_solve_shifted(self, sigma, rhs, tol, out=None):
+        n = rhs.shape[0]
+        x = torch.empty_like(rhs) if out is None else out
+        st = _SolveStats()
+        rc = self._check(self.lib.mg_solve_shifted(self.h, n, _dbl(sigma), _ptr(rhs), _ptr(x), float(tol),
+                                                   C.byref(st)), allow_warn=True)
+        info = {"iters": list(st.iters)[:n], "relres": list(st.relres)[:n], "coarse_iters": st.coarse_iters,
+                "converged": rc == 0}
+        return x, info
+
+    def rqi_lowmodes(self, n_eig, tol, V0=None, out=None):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        V = torch.empty((n_eig, 12, self.V), dtype=torch.complex128, device=dev) if out is None else out
+        lam = (C.c_double * n_eig)()
+        res = (C.c_double * n_eig)()
+        st = _RQIStats()
+        n_v0 = 0 if V0 is None else int(V0.shape[0])
+        rc = self._check(self.lib.rqi_lowmodes(self.h, int(n_eig), float(tol), lam, _ptr(V), res, _ptr(V0), n_v0,
+                                               C.byref(st)), allow_warn=True)
+        info = {f[0]: getattr(st, f[0]) for f in _RQIStats._fields_}
+        info["converged"] = rc == 0
+        return list(lam), V, list(res), info
+
+    def get_interp(self):
+        P = torch.empty((self.nv, 12, self.V), dtype=torch.complex128, device="cuda")
+        self._check(self.lib.mg_get_interp(self.h, _ptr(P)))
+        return P
+
+    def get_coarse(self):
+        n2 = 2 * self.nv
+        Qc = torch.empty((self.n_agg, 5, n2, n2), dtype=torch.complex128, device="cuda")
+        self._check(self.lib.mg_get_coarse(self.h, _ptr(Qc)))
+        return Qc
+
+    def restrict(self, f):
+        c = torch.empty((f.shape[0], self.n_agg, 2 * self.nv), dtype=torch.complex128, device=f.device)
+        self._check(self.lib.mg_restrict(self.h, f.shape[0], _ptr(f), _ptr(c)))
+        return c
+
+    def prolong(self, c):
+        f = torch.empty((c.shape[0], 12, self.V), dtype=torch.complex128, device=c.device)
+        self._check(self.lib.mg_prolong(self.h, c.shape[0], _ptr(c), _ptr(f)))
+        return f
+
+    def coarse_apply(self, sigma, x):
+        y = torch.empty_like(x)
+        self._check(self.lib.mg_coarse_apply(self.h, x.shape[0], _dbl(sigma), _ptr(x), _ptr(y)))
+        return y
+
+    def smooth(self, sigma, r, steps):
+        z = torch.empty_like(r)
+        self._check(self.lib.mg_smooth(self.h, r.shape[0], _dbl(sigma), _ptr(r), _ptr(z), int(steps)))
+        return z
+
+    def cycle(self, sigma, r):
+        z = torch.empty_like(r)
+        self._check(self.lib.mg_cycle(self.h, r.shape[0], _dbl(sigma), _ptr(r), _ptr(z)))
+        return z

@@ -1,0 +1,199 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: FP64 kernels agree with the FP64 oracle to a few units of
+rounding times the operator norm (1e-12 relative); FP32 kernels to 2e-6
+relative (24-bit mantissa, sums of <= 9 * 12 terms); solves and eigenpairs to
+the requested tolerances (eigenvalues relative 1e-10)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import lqsynth
+from oracle import mg as M
+from oracle.dirac import Lattice, WilsonOp, dense_Q
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "m0.json")
+
+
+def _ctx(dims, bc):
+    from paper_1509_06865_amd import Context
+    return Context(dims, bc)
+
+
+def dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def tiny(name):
+    cfg = json.load(open(GOLDEN))[name]
+    return tuple(cfg["dims"]), cfg["t_bc"], cfg["eps"], cfg["field_seed"], cfg["m0"]
+
+
+# ---------------------------------------------------------------- q_apply ----
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), -1), ((6, 4, 2, 10), 1), ((8, 8, 8, 8), -1),
+                                     ((3, 5, 2, 7), -1)])
+def test_q_apply_fp64_matches_oracle(dims, bc):
+    U = lqsynth.gauge_field(dims, 0.3, 5)
+    x = lqsynth.gaussian_spinors(3, dims, 6)
+    lat = Lattice(dims, bc)
+    ref = WilsonOp(U, -0.2, lat).Q(x)
+    c = _ctx(dims, bc)
+    y = host(c.q_apply(dev(U), -0.2, dev(x)))
+    torch.cuda.synchronize()
+    assert relmax(y, ref) < 1e-13
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), 1), ((6, 4, 2, 10), -1)])
+def test_q_apply_fp32_matches_oracle(dims, bc):
+    U = lqsynth.gauge_field(dims, 0.3, 7)
+    x = lqsynth.gaussian_spinors(2, dims, 8)
+    lat = Lattice(dims, bc)
+    ref = WilsonOp(U, 0.1, lat).Q(x)
+    c = _ctx(dims, bc)
+    y = host(c.q_apply(dev(U, torch.complex64), 0.1, dev(x, torch.complex64)))
+    assert relmax(y, ref) < 2e-6
+
+
+def test_q_apply_many_rhs_chunks():
+    dims = (4, 4, 2, 4)
+    U = lqsynth.gauge_field(dims, 0.3, 9)
+    x = lqsynth.gaussian_spinors(19, dims, 10)          # more than one 16-wide launch
+    ref = WilsonOp(U, -0.1, Lattice(dims, -1)).Q(x)
+    y = host(_ctx(dims, -1).q_apply(dev(U), -0.1, dev(x)))
+    assert relmax(y, ref) < 1e-13
+
+
+# ------------------------------------------------------- multigrid pieces ----
+@pytest.fixture(scope="module", params=[0, 1], ids=["fp64", "mixed"])
+def hier(request):
+    dims, bc, eps, seed, m0 = tiny("tiny_periodic")
+    U = lqsynth.gauge_field(dims, eps, seed)
+    lat = Lattice(dims, bc)
+    op = WilsonOp(U, m0, lat)
+    agg = (2, 2, 2, 2)
+    tv0 = lqsynth.gaussian_spinors(8, dims, 102)
+    from paper_1509_06865_amd import MGParams
+    prm = MGParams(precision=request.param, coarse_m=128, coarse_tol=1e-10, coarse_restarts=2, n_setup=3)
+    c = _ctx(dims, bc)
+    c.mg_setup(dev(U), m0, agg, dev(tv0), prm)
+    P = host(c.get_interp())
+    ag = M.Aggregation(lat, agg)
+    return dict(c=c, U=U, lat=lat, op=op, ag=ag, P=P, m0=m0, dims=dims, prec=request.param, prm=prm)
+
+
+def _tol(h):
+    return 1e-12 if h["prec"] == 0 else 3e-6
+
+
+def test_interp_orthonormal_per_aggregate_half(hier):
+    Pb = hier["ag"].to_blocks(hier["P"])                # [Nv, nA, 2, n]
+    G = np.einsum("ianx,janx->anij", Pb.conj(), Pb)
+    assert np.abs(G - np.eye(Pb.shape[0])).max() < 1e-12
+
+
+def test_coarse_operator_matches_galerkin_product(hier):
+    ref = M.coarse_operator(hier["op"], hier["ag"], hier["P"])[:, :5]
+    Qc = host(hier["c"].get_coarse())
+    assert relmax(Qc, ref) < _tol(hier) * 3
+
+
+def test_restrict_prolong_match(hier):
+    f = lqsynth.gaussian_spinors(2, hier["dims"], 11)
+    c = host(hier["c"].restrict(dev(f)))
+    ref = M.restrict(hier["P"], hier["ag"], f)
+    assert relmax(c, ref) < _tol(hier)
+    g = host(hier["c"].prolong(dev(ref)))
+    assert relmax(g, M.prolong(hier["P"], hier["ag"], ref)) < _tol(hier)
+
+
+def test_coarse_apply_matches(hier):
+    Qc = M.coarse_operator(hier["op"], hier["ag"], hier["P"])
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((2, hier["ag"].nA, 16)) + 1j * rng.standard_normal((2, hier["ag"].nA, 16))
+    sig = [0.0, 0.031]
+    y = host(hier["c"].coarse_apply(sig, dev(x)))
+    ref = np.stack([M.coarse_apply(Qc, hier["ag"], x[k], sig[k]) for k in range(2)])
+    assert relmax(y, ref) < _tol(hier) * 3
+
+
+def test_sap_smoother_matches(hier):
+    r = lqsynth.gaussian_spinors(2, hier["dims"], 13)
+    sig = [0.0, 0.05]
+    z = host(hier["c"].smooth(sig, dev(r), 2))
+    ref = np.stack([M.sap(hier["op"], hier["ag"], sig[k], r[k], 2, 4) for k in range(2)])
+    assert relmax(z, ref) < (1e-11 if hier["prec"] == 0 else 2e-5)
+
+
+def test_cycle_matches(hier):
+    mg = M.TwoLevel(hier["op"], (2, 2, 2, 2), M.MGParams(pre=0, post=3, n_mr=4, coarse_m=128,
+                                                          coarse_tol=1e-10, coarse_restarts=2))
+    mg.P = hier["P"]
+    mg.Qc = M.coarse_operator(hier["op"], hier["ag"], hier["P"])
+    r = lqsynth.gaussian_spinors(2, hier["dims"], 14)
+    sig = [0.0, 0.02]
+    z = host(hier["c"].cycle(sig, dev(r)))
+    ref = np.stack([mg.cycle(sig[k], r[k]) for k in range(2)])
+    assert relmax(z, ref) < (1e-8 if hier["prec"] == 0 else 5e-5)
+
+
+def test_solve_shifted_matches_dense(hier):
+    Qd = dense_Q(hier["U"], hier["m0"], hier["lat"])
+    b = lqsynth.gaussian_spinors(3, hier["dims"], 15)
+    sig = [0.0, 0.015, -0.04]
+    x, info = hier["c"].mg_solve_shifted(sig, dev(b), 1e-10)
+    x = host(x)
+    assert info["converged"], info
+    for k in range(3):
+        ref = np.linalg.solve(Qd - sig[k] * np.eye(Qd.shape[0]), b[k].ravel())
+        assert np.linalg.norm(x[k].ravel() - ref) / np.linalg.norm(ref) < 1e-8
+        assert info["relres"][k] < 1e-10
+
+
+# ------------------------------------------------------------- eigenpairs ----
+# With t antiperiodic the 8 lowest |lambda| lie in a dense cluster near 0.5 and
+# the damped shifts land inside it; with Nv = 8 the multigrid-preconditioned
+# FGMRES does not converge there (the oracle needs > 400 steps at sigma = 0.49),
+# with Nv = 16 it takes ~20.  That case therefore runs with 16 test vectors.
+@pytest.mark.parametrize("name,prec,nv", [("tiny_periodic", 0, 8), ("tiny_periodic", 1, 8),
+                                          ("tiny_antiperiodic", 1, 16)])
+def test_rqi_lowest_eight_match_dense(name, prec, nv):
+    dims, bc, eps, seed, m0 = tiny(name)
+    U = lqsynth.gauge_field(dims, eps, seed)
+    lat = Lattice(dims, bc)
+    from paper_1509_06865_amd import MGParams
+    c = _ctx(dims, bc)
+    c.mg_setup(dev(U), m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(nv, dims, 102)),
+               MGParams(precision=prec, coarse_m=128, coarse_tol=1e-8, coarse_restarts=2, n_setup=4,
+                        rqi_block=4, rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1))
+    n_extra = max(0, 8 + 4 - nv)
+    V0 = dev(lqsynth.gaussian_spinors(n_extra, dims, 103)) if n_extra else None
+    lam, V, res, info = c.rqi_lowmodes(8, 1e-10, V0=V0)
+    assert info["converged"], info
+    ev = np.linalg.eigvalsh(dense_Q(U, m0, lat))
+    ref = ev[np.argsort(np.abs(ev))][:8]
+    ref = np.array(sorted(ref, key=lambda v: (abs(v), v)))
+    lam = np.array(lam)
+    assert np.abs(lam - ref).max() / np.abs(ref).max() < 1e-10
+    # residuals recomputed with the oracle's Q
+    Vh = host(V)
+    op = WilsonOp(U, m0, lat)
+    Qv = op.Q(Vh)
+    for i in range(8):
+        nv = np.linalg.norm(Vh[i])
+        assert abs(nv - 1) < 1e-12
+        assert np.linalg.norm(Qv[i] - lam[i] * Vh[i]) <= 2e-10
+    G = np.einsum("ian,jan->ij", Vh.conj(), Vh)
+    assert np.abs(G - np.eye(8)).max() < 1e-10

@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every function include/lqmg.h declares
+(no compute call: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lqmg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?\**\s*\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "typedef")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("q_apply", "mg_setup", "mg_solve_shifted", "rqi_lowmodes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1509_06865_amd import lqmg
+    if not os.path.exists(lqmg.library_path()):
+        pytest.fail("liblqmg.so is not built (python -m paper_1509_06865_amd.build)")
+    lib = ctypes.CDLL(lqmg.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(lqmg.EXPORTED) == declared_functions()
+
+
+def test_params_struct_matches_library_defaults():
+    from paper_1509_06865_amd import lqmg
+    lib = lqmg.load()
+    p = lqmg._Params()
+    assert lib.lq_params_default(ctypes.byref(p)) == 0
+    assert p.rqi_block == 16 and p.fgmres_m == 10 and abs(p.rqi_solve_tol - 1e-8) < 1e-20
+    assert lib.lq_params_default(None) == -1
+
+
+def test_create_rejects_bad_arguments():
+    from paper_1509_06865_amd import lqmg
+    lib = lqmg.load()
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int * 4)(4, 4, 1, 4)
+    assert lib.lq_create(ctypes.byref(h), bad, -1, None) == -1
+    good = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.lq_create(ctypes.byref(h), good, 0, None) == -1
