@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark: lowest-|lambda| eigenpairs of the Hermitian Wilson-Dirac operator
+on one MI355X (RQI + gamma5-aggregation multigrid), plus the Dirac-apply
+bandwidth.
+
+One step = mg_setup (adaptive setup from random test vectors) + rqi_lowmodes
+(Alg. 1 to the target residual) on a synthetic SU(3) field of the workload's
+shape, inputs already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps 1] [--warmup 0] [--workload large|medium|small]
+"""
+import os
+
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+import numpy as np  # noqa: E402
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time for lowest-100 eigenpairs of Q at 32^3x64, tol 1e-10; Dirac-apply HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+# Workloads: lattice, field, aggregation, Nv, N_eig, tolerance.  Masses come
+# from tests/golden/m0.json (written by tests/golden/make_m0.py).
+WORKLOADS = {
+    "large": dict(golden="large", agg=(4, 4, 4, 4), nv=24, n_eig=100, tol=1e-10, guard=8,
+                  params=dict(rqi_block=8, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=4,
+                              coarse_tol=0.05)),
+    "medium": dict(golden="medium", agg=(4, 4, 4, 4), nv=20, n_eig=50, tol=1e-10, guard=6,
+                   params=dict(rqi_block=16, fgmres_m=10, n_setup=4, coarse_m=40, coarse_restarts=4,
+                               coarse_tol=0.05)),
+    "small": dict(golden="tiny_periodic", agg=(2, 2, 2, 2), nv=8, n_eig=8, tol=1e-10, guard=4,
+                  params=dict(rqi_block=4, fgmres_m=10, n_setup=4, coarse_m=128, coarse_restarts=2,
+                              coarse_tol=1e-8)),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def load_golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", "m0.json")) as f:
+        return json.load(f)[name]
+
+
+def device_gaussian(n, dims, seed, torch):
+    """Seeded complex Gaussian start vectors drawn on the device (input
+    generation only; the large lattices make host generation slow)."""
+    V = int(np.prod(dims))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    re = torch.randn((n, 12, V), generator=g, device="cuda", dtype=torch.float64)
+    im = torch.randn((n, 12, V), generator=g, device="cuda", dtype=torch.float64)
+    return torch.complex(re, im) / np.sqrt(2.0)
+
+
+def time_q_apply(ctx, U, m0, x, reps, torch):
+    """Average device time of one q_apply launch (HIP events on the context's stream)."""
+    st = ctx.stream
+    for _ in range(3):
+        ctx.q_apply(U, m0, x)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(st)
+    for _ in range(reps):
+        ctx.q_apply(U, m0, x)
+    stop.record(st)
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps / 1e3
+
+
+def cpu_baseline(U_host, m0, dims, t_bc, x_host):
+    """The oracle's FP64 Q apply (definition route) on the full lattice, timed
+    on the host: the CPU reference for the Dirac-apply part of the metric."""
+    from oracle.dirac import Lattice, apply_Q
+    lat = Lattice(dims, t_bc)
+    lat.tables()                                   # neighbour tables built outside the timing
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        apply_Q(U_host, m0, x_host, lat)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 3:
+            break
+    t = (time.perf_counter() - t0) / reps
+    V = int(np.prod(dims))
+    return {"value": round(960.0 * V / t / 1e9, 3), "unit": "GB/s (Dirac apply, FP64, algorithmic bytes)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{reps} FP64 Q applies of the oracle's numpy definition on the full {dims} lattice "
+                      f"({t:.2f} s each); the eigensolve itself is not run on the CPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-eig", type=int, default=None, help="override the workload's eigenpair count")
+    ap.add_argument("--guard", type=int, default=None)
+    ap.add_argument("--nv", type=int, default=None)
+    ap.add_argument("--max-sweeps", type=int, default=40)
+    ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              f"described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import Context, MGParams
+
+    wl = dict(WORKLOADS[args.workload])
+    wl["params"] = dict(wl["params"])
+    for key in ("n_eig", "guard", "nv"):
+        if getattr(args, key) is not None:
+            wl[key] = getattr(args, key)
+    for kv in args.param:
+        k, v = kv.split("=")
+        wl["params"][k] = float(v) if ("." in v or "e" in v) else int(v)
+    gold = load_golden(wl["golden"])
+    dims, t_bc, eps, seed, m0 = tuple(gold["dims"]), gold["t_bc"], gold["eps"], gold["field_seed"], gold["m0"]
+    V = int(np.prod(dims))
+    log(f"workload {args.workload}: dims {dims} t_bc {t_bc} eps {eps} m0 {m0} Nv {wl['nv']} n_eig {wl['n_eig']}")
+    t0 = time.time()
+    U_host = lqsynth.gauge_field(dims, eps, seed)
+    U = torch.from_numpy(U_host).cuda()
+    log(f"gauge field ready ({time.time() - t0:.1f} s)")
+    tv0 = device_gaussian(wl["nv"], dims, seed + 1, torch)
+    n_work = wl["n_eig"] + wl["guard"]
+    n_v0 = n_work - min(wl["nv"], n_work)
+    V0 = device_gaussian(n_v0, dims, seed + 2, torch) if n_v0 > 0 else None
+    prm = MGParams(precision=1, rqi_guard=wl["guard"], rayleigh_ritz=1, rqi_max_sweeps=args.max_sweeps,
+                   **wl["params"])
+    ctx = Context(dims, t_bc)
+
+    # Dirac apply bandwidth (FP64 and FP32), device time per launch
+    x = device_gaussian(1, dims, seed + 3, torch)
+    t64 = time_q_apply(ctx, U, m0, x, 20, torch)
+    t32 = time_q_apply(ctx, U.to(torch.complex64), m0, x.to(torch.complex64), 20, torch)
+    gbs64, gbs32 = 960.0 * V / t64 / 1e9, 480.0 * V / t32 / 1e9
+    log(f"q_apply FP64 {t64 * 1e3:.3f} ms = {gbs64:.0f} GB/s ; FP32 {t32 * 1e3:.3f} ms = {gbs32:.0f} GB/s")
+
+    def step():
+        ctx.mg_setup(U, m0, wl["agg"], tv0, prm)
+        t_setup = time.time()
+        lam, Vv, res, info = ctx.rqi_lowmodes(wl["n_eig"], wl["tol"], V0=V0)
+        return lam, res, info, t_setup
+
+    os.environ["LQMG_VERBOSE"] = "1"
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    times, setups = [], []
+    for s in range(args.steps):
+        torch.cuda.synchronize()
+        a = time.time()
+        lam, res, info, t_setup = step()
+        torch.cuda.synchronize()
+        b = time.time()
+        times.append(b - a)
+        setups.append(t_setup - a)
+        log(f"step {s + 1}/{args.steps}: {b - a:.2f} s (setup {t_setup - a:.2f} s), converged {info['converged']}, "
+            f"sweeps {info['sweeps']}, solves {info['solves']}, fgmres its {info['fgmres_iters']}")
+    T = max(times)
+    out = {
+        "metric": METRIC, "value": round(T, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * T, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (RQI, FGMRES) + f32 (multigrid)", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} t_bc={t_bc} eps={eps} "
+                               f"m0={m0}, 2-level MG {wl['agg']} aggregates Nv={wl['nv']}, lowest {wl['n_eig']} "
+                               f"eigenpairs at residual {wl['tol']}",
+                   "n_eig": wl["n_eig"], "tol": wl["tol"], "converged": info["converged"],
+                   "smallest_abs_lambda": float(abs(lam[0])), "largest_abs_lambda": float(abs(lam[-1])),
+                   "max_residual": float(max(res)), "setup_s": round(max(setups), 3),
+                   "rqi_s": round(T - max(setups), 3), "sweeps": info["sweeps"], "solves": info["solves"],
+                   "fgmres_iters": info["fgmres_iters"],
+                   "phase_s": {k: round(info[k], 3) for k in ("t_solve", "t_ortho", "t_rebuild", "t_rq")},
+                   "dirac_apply_gbs": {"fp64": round(gbs64, 1), "fp32": round(gbs32, 1)}},
+        "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_wilson<double> (q_apply FP64), 960 B/site algorithmic"},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle Q apply on the host)")
+        x_host = x[0].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(U_host, m0, dims, t_bc, x_host)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,6 +77,12 @@ typedef struct {
   int rayleigh_ritz;    /* RQI: 1 = Rayleigh-Ritz over all vectors after each sweep */
   int rqi_guard;        /* RQI: vectors iterated beyond n_eig (guard band against
                            missed modes); the n_eig smallest |lambda| are returned */
+  int rqi_solve_restarts; /* RQI: FGMRES restarts per shifted solve; RQI needs the
+                           direction of (Q - sigma)^-1 v, not a small residual, and
+                           near convergence the system is nearly singular */
+  int rqi_deflate;      /* RQI: 1 = before each multigrid cycle, solve Q - sigma
+                           exactly on the span of the current eigenvector
+                           approximations (Galerkin correction, FP64) */
 } lq_mg_params;
 
 typedef struct {
@@ -146,6 +152,15 @@ int mg_solve_shifted(lq_ctx *ctx, int n_rhs, const double *sigma,
 int rqi_lowmodes(lq_ctx *ctx, int n_eig, double tol, double *lambda,
                  lq_c128 *V, double *resid, const lq_c128 *V0, int n_v0,
                  lq_rqi_stats *st);
+
+/* Inner products out[i*nw + k] = <E_i, W_k> = sum_e conj(E_i[e]) W_k[e] of nb
+ * device vectors E [nb][n] against nw device vectors W [nw][n] (complex128,
+ * n elements each; 1 <= nb <= 192, 1 <= nw <= 16); out: host [nb][nw].  These
+ * are the Gram-Schmidt / Rayleigh-Ritz products of Alg. 1 (sec. 2.1) and of
+ * the projections A_ij = <v_i|Q|v_j> of sec. 3.2; FP64 matrix cores.
+ * Errors: LQ_ERR_ARG. */
+int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
+                      long long n, lq_c128 *out);
 
 /* ---- inspection of the hierarchy (parity tests; sec. 2 objects) ---------- */
 /* Number of test vectors Nv and aggregates nA of the current hierarchy. */

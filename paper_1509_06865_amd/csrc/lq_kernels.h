@@ -45,6 +45,15 @@ void launch_arnoldi_update(int j, int m, int nrhs, const c128 *h1, const c128 *h
                            double *cs, c128 *sn, c128 *g, const double *bn, double tol, int *active, int *kk,
                            c128 *coef, int *bad, hipStream_t st);
 void launch_arnoldi_solve(int m, int nrhs, const c128 *H, const c128 *g, const int *kk, c128 *Y, hipStream_t st);
+// ---- shared-basis products (gram.hip), FP64 -----------------------------------
+// out[i][k] = <E_i, W_k> for i < nb (<= 192), k < nw (<= 16); E_i at E + i*estride,
+// W_k at W + k*wstride, vectors of n complex.  FP64 MFMA, split over n.
+void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W, long long wstride, long long n,
+                 c128 *out /*device [nb][nw]*/, c128 *scratch, hipStream_t st);
+size_t gram_scratch_elems(long long n);
+// U_k (+)= sum_i Y[i][k] E_i for k < nw; Y device [nb][nw].
+void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128 *Y, c128 *U, long long ustride,
+                    long long n, bool accumulate, hipStream_t st);
 // Scratch size (in c128 elements) that launch_dots needs.
 size_t dots_scratch_elems(int nv, int nrhs);
 // y_k = a_k * x_k (+ y_k if accumulate), a device [nrhs] c128

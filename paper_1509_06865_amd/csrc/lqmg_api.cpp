@@ -10,6 +10,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -56,6 +58,12 @@ template <typename T> struct DevBuf {
 
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Progress lines on stderr when LQMG_VERBOSE is set (long calls stay observable).
+bool verbose() {
+  static const bool v = std::getenv("LQMG_VERBOSE") != nullptr;
+  return v;
 }
 
 template <typename T> struct MGData {
@@ -122,7 +130,7 @@ struct lq_ctx {
   DevBuf<int> blocks[2];
   int nblocks[2] = {0, 0};
   DevBuf<int> status;
-  DevBuf<c128> red_scratch, red_out, coef;
+  DevBuf<c128> red_scratch, red_out, coef, gram_scratch;
   DevBuf<int> ints;                 // small per-call integer arrays
   // workspaces
   KrylovWork<double> fine_kw;
@@ -137,7 +145,8 @@ struct lq_ctx {
   DevBuf<c64> parts32, pc32;
   DevBuf<c128> eig;                 // RQI vectors, blocked FP64 [n][12][V]
   DevBuf<c128> sel;                 // vectors that build P [Nv][12][V]
-  DevBuf<c128> rr_buf;              // Rayleigh-Ritz rotated vectors
+  DevBuf<c128> rr_gather;
+  DevBuf<c128> defl_tmp, defl_u, defl_r;   // Galerkin correction work           // Rayleigh-Ritz: gathered unconverged vectors
   DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
   int coarse_iters = 0;
 };
@@ -184,6 +193,31 @@ void scale(lq_ctx *c, const std::vector<cd> &a, const cplx<T> *x, long long xs, 
   c128 *d = c->coef.get((size_t)nrhs);
   LQ_HIP(hipMemcpyAsync(d, a.data(), (size_t)nrhs * sizeof(c128), hipMemcpyHostToDevice, c->st));
   launch_scale<T>(d, x, xs, y, ys, n, nrhs, acc, c->st);
+  sync(c);
+}
+
+// <E_i, W_k> for a shared basis E (read once), returned as [nb][nw]
+std::vector<cd> gram(lq_ctx *c, int nb, const c128 *E, long long estride, int nw, const c128 *W, long long wstride,
+                     long long n) {
+  std::vector<cd> out((size_t)nb * nw);
+  if (nb == 0 || nw == 0) return out;
+  c128 *sc = c->gram_scratch.get(gram_scratch_elems(n));
+  c128 *o = c->red_out.get((size_t)nb * nw);
+  launch_gram(nb, E, estride, nw, W, wstride, n, o, sc, c->st);
+  LQ_HIP(hipMemcpyAsync(out.data(), o, out.size() * sizeof(c128), hipMemcpyDeviceToHost, c->st));
+  sync(c);
+  return out;
+}
+
+// U_k (+)= sign * sum_i Y[i][k] E_i, Y given on the host as [nb][nw]
+void combine(lq_ctx *c, int nb, const c128 *E, long long estride, int nw, const std::vector<cd> &Y, double sign,
+             c128 *U, long long ustride, long long n, bool accumulate) {
+  if (nb == 0 || nw == 0) return;
+  std::vector<cd> Ys(Y.size());
+  for (size_t e = 0; e < Y.size(); ++e) Ys[e] = sign * Y[e];
+  c128 *d = c->coef.get(Ys.size());
+  LQ_HIP(hipMemcpyAsync(d, Ys.data(), Ys.size() * sizeof(c128), hipMemcpyHostToDevice, c->st));
+  launch_combine(nb, E, estride, nw, d, U, ustride, n, accumulate, c->st);
   sync(c);
 }
 
@@ -460,8 +494,11 @@ void orthonormalise(lq_ctx *c, c128 *F, int n) {
 }
 
 // FGMRES for (Q - sigma_k) x_k = b_k, FP64, blocked layout.
+struct Deflation;
+void deflated_precond(lq_ctx *c, const Deflation &D, const double *sig, const c128 *in, c128 *out, int nrhs);
+
 bool solve_shifted(lq_ctx *c, int nrhs, const double *sig, const c128 *b, c128 *x, double tol, int *iters,
-                   double *relres) {
+                   double *relres, int max_restarts, const Deflation *D = nullptr) {
   const long long n = 12LL * c->g.V;
   Shifts S = shifts_of(sig, nrhs);
   std::vector<double> sv(sig, sig + nrhs);
@@ -469,12 +506,15 @@ bool solve_shifted(lq_ctx *c, int nrhs, const double *sig, const c128 *b, c128 *
   ops.apply = [=](const c128 *in, c128 *out) {
     launch_wilson<double>(c->g, c->U64.p, in, out, nullptr, c->m0, S, nrhs, W_QSHIFT, c->st);
   };
-  ops.precond = [=](const c128 *in, c128 *out) { precond64(c, sv.data(), in, out, nrhs); };
+  if (D)
+    ops.precond = [=](const c128 *in, c128 *out) { deflated_precond(c, *D, sv.data(), in, out, nrhs); };
+  else
+    ops.precond = [=](const c128 *in, c128 *out) { precond64(c, sv.data(), in, out, nrhs); };
   ops.resid = [=](const c128 *bb, const c128 *xx, c128 *r) {
     launch_wilson<double>(c->g, c->U64.p, xx, r, bb, c->m0, S, nrhs, W_RESID, c->st);
   };
-  return gmres_batched<double>(c, c->fine_kw, n, nrhs, ops, b, x, c->p.fgmres_m, c->p.fgmres_restarts, tol, iters,
-                               relres, 1);
+  return gmres_batched<double>(c, c->fine_kw, n, nrhs, ops, b, x, c->p.fgmres_m, max_restarts, tol, iters, relres,
+                               1);
 }
 
 // Eigen-decomposition of a Hermitian n x n matrix (row-major) by cyclic
@@ -527,7 +567,48 @@ void jacobi_eigh(int n, std::vector<cd> &A, std::vector<cd> &Vm) {
 
 // Rayleigh-Ritz on span(E) (E orthonormal, n fields): H = E^dag Q E, H = C w C^dag,
 // E <- E C ordered by (|w|, w); lam receives w.
-void rayleigh_ritz(lq_ctx *c, c128 *E, int n, std::vector<double> &lam) {
+void rayleigh_ritz(lq_ctx *c, const c128 *E, int n, std::vector<double> &lam, const std::vector<c128 *> &dst);
+
+// Rayleigh-Ritz restricted to the vectors U of E (nw fields): they are first
+// made orthonormal to the locked vectors (eps <= tol) and to each other
+// (Gram-Schmidt twice, index order), gathered, rotated to Ritz vectors and
+// written back to their slots in order of increasing |Ritz value|.
+void rayleigh_ritz_subset(lq_ctx *c, c128 *E, int nw, const std::vector<int> &U, const std::vector<double> &eps,
+                          double tol, std::vector<double> &lam) {
+  const long long V12 = 12LL * c->g.V;
+  const int n = (int)U.size();
+  c128 *G = c->rr_gather.get((size_t)n * V12);
+  for (int q = 0; q < n; ++q) copy<double>(c, G + q * V12, E + U[q] * V12, V12);
+  std::vector<int> locked;
+  for (int i = 0; i < nw; ++i)
+    if (eps[i] <= tol) locked.push_back(i);
+  for (int q = 0; q < n; ++q) {
+    c128 *x = G + q * V12;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (!locked.empty()) {
+        auto h = dots<double>(c, nw, E, V12, 0, x, 0, V12, 1);
+        std::vector<cd> hl((size_t)nw, cd(0));
+        for (int j : locked) hl[j] = h[j];
+        axpys<double>(c, nw, E, V12, 0, hl, x, 0, V12, 1, -1.0);
+      }
+      if (q > 0) {
+        auto h = dots<double>(c, q, G, V12, 0, x, 0, V12, 1);
+        axpys<double>(c, q, G, V12, 0, h, x, 0, V12, 1, -1.0);
+      }
+    }
+    auto nr = norms<double>(c, x, V12, 1);
+    if (!(nr[0] > 0) || !std::isfinite(nr[0])) fail(LQ_ERR_NUMERIC, "vector collapsed before Rayleigh-Ritz");
+    scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, x, 0, x, 0, V12, 1, false);
+  }
+  std::vector<double> w(n);
+  std::vector<c128 *> dst(n);
+  for (int q = 0; q < n; ++q) dst[q] = E + U[q] * V12;
+  rayleigh_ritz(c, G, n, w, dst);
+  for (int q = 0; q < n; ++q) lam[U[q]] = w[q];
+  sync(c);
+}
+
+void rayleigh_ritz(lq_ctx *c, const c128 *E, int n, std::vector<double> &lam, const std::vector<c128 *> &dst) {
   const long long V12 = 12LL * c->g.V;
   c128 *QE = c->tmpA.get((size_t)kMaxRhs * V12);
   std::vector<cd> H((size_t)n * n);
@@ -535,7 +616,7 @@ void rayleigh_ritz(lq_ctx *c, c128 *E, int n, std::vector<double> &lam) {
   for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
     const int nk = std::min(kMaxRhs, n - j0);
     launch_wilson<double>(c->g, c->U64.p, E + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
-    auto d = dots<double>(c, n, E, V12, 0, QE, V12, V12, nk);     // d[i][k] = <E_i, Q E_{j0+k}>
+    auto d = gram(c, n, E, V12, nk, QE, V12, V12);                // d[i][k] = <E_i, Q E_{j0+k}>
     for (int i = 0; i < n; ++i)
       for (int k = 0; k < nk; ++k) H[(size_t)i * n + j0 + k] = d[(size_t)i * nk + k];
   }
@@ -554,19 +635,116 @@ void rayleigh_ritz(lq_ctx *c, c128 *E, int n, std::vector<double> &lam) {
     if (std::fabs(wa) != std::fabs(wb)) return std::fabs(wa) < std::fabs(wb);
     return wa < wb;
   });
-  // new E_j = sum_i C[i][o_j] E_i, written to a second buffer, then copied back
-  c128 *NE = c->rr_buf.get((size_t)n * V12);
-  zero<double>(c, NE, (size_t)n * V12);
+  // Ritz vector j = sum_i C[i][o_j] E_i, 16 at a time into a work buffer, then
+  // to its destination (which must not overlap E)
+  c128 *NE = c->tmpB.get((size_t)kMaxRhs * V12);
   for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
     const int nk = std::min(kMaxRhs, n - j0);
     std::vector<cd> h((size_t)n * nk);
     for (int i = 0; i < n; ++i)
       for (int k = 0; k < nk; ++k) h[(size_t)i * nk + k] = Cm[(size_t)i * n + o[j0 + k]];
-    axpys<double>(c, n, E, V12, 0, h, NE + j0 * V12, V12, V12, nk, 1.0);
+    combine(c, n, E, V12, nk, h, 1.0, NE, V12, V12, false);
+    for (int k = 0; k < nk; ++k) copy<double>(c, dst[j0 + k], NE + k * V12, V12);
   }
-  copy<double>(c, E, NE, (size_t)n * V12);
   for (int j = 0; j < n; ++j) lam[j] = H[(size_t)o[j] * n + o[j]].real();
   sync(c);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin correction on the span of the current eigenvector approximations.
+// With E = [e_1 .. e_n], A = E^dag Q E and G = E^dag E, the correction for
+// shift sigma is u = E (A - sigma G)^{-1} E^dag r: the exact solve of (Q - sigma)
+// restricted to span(E).  It is applied before the multigrid cycle, so the
+// near-null directions of Q - sigma that E approximates (the targets of the
+// shifted inversions, including clustered ones) are handled in FP64 by a
+// second, global coarse space built from the eigenvector approximations.
+// ---------------------------------------------------------------------------
+struct Deflation {
+  const c128 *E = nullptr;
+  int n = 0;
+  std::vector<cd> LU[kMaxRhs];       // LU factors of A - sigma_k G (row-major)
+  std::vector<int> piv[kMaxRhs];
+};
+
+// LU with partial pivoting, in place (row-major n x n).
+bool lu_factor(int n, std::vector<cd> &M, std::vector<int> &piv) {
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::abs(M[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(M[(size_t)i * n + k]) > best) { best = std::abs(M[(size_t)i * n + k]); p = i; }
+    piv[k] = p;
+    if (best == 0.0) return false;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(M[(size_t)k * n + j], M[(size_t)p * n + j]);
+    const cd d = M[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      const cd f = M[(size_t)i * n + k] / d;
+      M[(size_t)i * n + k] = f;
+      for (int j = k + 1; j < n; ++j) M[(size_t)i * n + j] -= f * M[(size_t)k * n + j];
+    }
+  }
+  return true;
+}
+
+void lu_solve(int n, const std::vector<cd> &M, const std::vector<int> &piv, cd *b) {
+  for (int k = 0; k < n; ++k) {
+    std::swap(b[k], b[piv[k]]);
+    for (int i = k + 1; i < n; ++i) b[i] -= M[(size_t)i * n + k] * b[k];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    cd v = b[i];
+    for (int j = i + 1; j < n; ++j) v -= M[(size_t)i * n + j] * b[j];
+    b[i] = v / M[(size_t)i * n + i];
+  }
+}
+
+// A = E^dag Q E and G = E^dag E for the n fields E (blocked layout, FP64).
+void projected_operator(lq_ctx *c, const c128 *E, int n, std::vector<cd> &A, std::vector<cd> &G) {
+  const long long V12 = 12LL * c->g.V;
+  c128 *QE = c->defl_tmp.get((size_t)kMaxRhs * V12);
+  A.assign((size_t)n * n, cd(0));
+  G.assign((size_t)n * n, cd(0));
+  Shifts z = shifts_of(nullptr, 0);
+  for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, n - j0);
+    launch_wilson<double>(c->g, c->U64.p, E + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+    auto a = gram(c, n, E, V12, nk, QE, V12, V12);
+    auto g = gram(c, n, E, V12, nk, E + j0 * V12, V12, V12);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < nk; ++k) {
+        A[(size_t)i * n + j0 + k] = a[(size_t)i * nk + k];
+        G[(size_t)i * n + j0 + k] = g[(size_t)i * nk + k];
+      }
+  }
+}
+
+// out = u + B_sigma(in - (Q - sigma) u) with u the Galerkin correction on span(E).
+void deflated_precond(lq_ctx *c, const Deflation &D, const double *sig, const c128 *in, c128 *out, int nrhs) {
+  const long long n = 12LL * c->g.V;
+  auto cc = gram(c, D.n, D.E, n, nrhs, in, n, n);                    // [D.n][nrhs]
+  std::vector<cd> Y(cc.size()), col(D.n);
+  for (int k = 0; k < nrhs; ++k) {
+    for (int i = 0; i < D.n; ++i) col[i] = cc[(size_t)i * nrhs + k];
+    lu_solve(D.n, D.LU[k], D.piv[k], col.data());
+    for (int i = 0; i < D.n; ++i) Y[(size_t)i * nrhs + k] = col[i];
+  }
+  c128 *U = c->defl_u.get((size_t)kMaxRhs * n), *R = c->defl_r.get((size_t)kMaxRhs * n);
+  combine(c, D.n, D.E, n, nrhs, Y, 1.0, U, n, n, false);
+  launch_wilson<double>(c->g, c->U64.p, U, R, in, c->m0, shifts_of(sig, nrhs), nrhs, W_RESID, c->st);
+  precond64(c, sig, R, out, nrhs);
+  launch_multi_axpy<double>(1, U, 0, n, c->plus_one.p, out, n, n, nrhs, 1.0, c->st);
+}
+
+void deflation_factor(Deflation &D, const std::vector<cd> &A, const std::vector<cd> &G, const double *sig,
+                      int nrhs) {
+  const int n = D.n;
+  for (int k = 0; k < nrhs; ++k) {
+    D.LU[k].resize((size_t)n * n);
+    for (size_t e = 0; e < (size_t)n * n; ++e) D.LU[k][e] = A[e] - sig[k] * G[e];
+    if (!lu_factor(n, D.LU[k], D.piv[k])) fail(LQ_ERR_NUMERIC, "projected shifted matrix is singular");
+  }
 }
 
 void check_ctx(lq_ctx *c) {
@@ -619,9 +797,11 @@ int lq_params_default(lq_mg_params *p) {
   p->n_setup = 4;
   p->rqi_block = 16;
   p->rqi_max_sweeps = 30;
-  p->rqi_solve_tol = 1e-8;
+  p->rqi_solve_tol = 1e-6;
   p->rayleigh_ritz = 1;
   p->rqi_guard = 2;
+  p->rqi_solve_restarts = 1;
+  p->rqi_deflate = 1;
   return LQ_OK;
 }
 
@@ -764,6 +944,11 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
       }
       orthonormalise(c, W, n_tv);
       rebuild(c, W);
+      if (verbose()) {
+        std::fprintf(stderr, "[lqmg] setup pass %d/%d done, coarse its so far %d\n", it + 1, p.n_setup,
+                     c->coarse_iters);
+        std::fflush(stderr);
+      }
     }
     sync(c);
     return LQ_OK;
@@ -783,7 +968,7 @@ int mg_solve_shifted(lq_ctx *c, int n_rhs, const double *sigma, const lq_c128 *r
     int its[kMaxRhs];
     double rr[kMaxRhs];
     c->coarse_iters = 0;
-    bool ok = solve_shifted(c, n_rhs, sigma, b, xb, tol, its, rr);
+    bool ok = solve_shifted(c, n_rhs, sigma, b, xb, tol, its, rr, c->p.fgmres_restarts);
     launch_permute<double>(c->g, xb, (c128 *)x, n_rhs, false, c->st);
     sync(c);
     if (st) {
@@ -823,15 +1008,24 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     orthonormalise(c, E, nw);
     std::vector<double> lam(nw, 0.0), eps(nw, 1.0);
     c128 *SEL = c->sel.get((size_t)Nv * V12);
-    auto rebuild_from = [&]() {
+    // P from the current approximations (Alg. 1: "update v_i in P").  With
+    // more vectors than Nv it takes the Nv whose lambda lies nearest to one of
+    // the shifts about to be solved for (ties: lower index), so that the
+    // coarse space holds the near-null vectors of those Q - sigma.
+    auto rebuild_from = [&](const std::vector<double> &shifts) {
       double t0 = now();
       std::vector<int> idx;
       if (nw <= Nv) {
         for (int i = 0; i < nw; ++i) idx.push_back(i);
       } else {
+        std::vector<double> dist(nw);
+        for (int i = 0; i < nw; ++i) {
+          dist[i] = 1e300;
+          for (double s : shifts) dist[i] = std::min(dist[i], std::fabs(lam[i] - s));
+        }
         std::vector<int> o(nw);
         for (int i = 0; i < nw; ++i) o[i] = i;
-        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return std::fabs(lam[a]) < std::fabs(lam[b]); });
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return dist[a] < dist[b]; });
         idx.assign(o.begin(), o.begin() + Nv);
         std::sort(idx.begin(), idx.end());
       }
@@ -850,7 +1044,7 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         if (!(eps[o[q]] <= tol)) return false;
       return true;
     };
-    rebuild_from();
+    rebuild_from({0.0});
     c128 *X = c->tmpB.get((size_t)kMaxRhs * V12);
     c128 *B = c->tmpA.get((size_t)kMaxRhs * V12);
     const int nb = c->p.rqi_block;
@@ -884,42 +1078,93 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
           sig[q] = lam[i] * std::max(1.0 - eps[i], 0.0);        // damped shift (Alg. 1)
           copy<double>(c, B + q * V12, E + i * V12, V12);
         }
+        if (nw > Nv) rebuild_from(sig);
         double t0 = now();
+        Deflation D;
+        if (c->p.rqi_deflate) {
+          std::vector<cd> A, G;
+          projected_operator(c, E, nw, A, G);
+          D.E = E;
+          D.n = nw;
+          deflation_factor(D, A, G, sig.data(), nk);
+        }
         int its[kMaxRhs];
         double rr[kMaxRhs];
-        solve_shifted(c, nk, sig.data(), B, X, c->p.rqi_solve_tol, its, rr);
+        solve_shifted(c, nk, sig.data(), B, X, c->p.rqi_solve_tol, its, rr, c->p.rqi_solve_restarts,
+                      c->p.rqi_deflate ? &D : nullptr);
         for (int q = 0; q < nk; ++q) S.fgmres_iters += its[q];
         S.solves += nk;
         S.t_solve += now() - t0;
         t0 = now();
+        // Gram-Schmidt (twice): first against the vectors outside the block
+        // that precede each member or are locked, all block members at once ...
+        std::vector<char> inblk(nw, 0);
+        for (int q = 0; q < nk; ++q) inblk[todo[q0 + q]] = 1;
+        for (int pass = 0; pass < 2; ++pass) {
+          auto h = gram(c, nw, E, V12, nk, X, V12, V12);                // h[j][q] = <E_j, X_q>
+          for (int j = 0; j < nw; ++j)
+            for (int q = 0; q < nk; ++q) {
+              const int i = todo[q0 + q];
+              const bool use = !inblk[j] && (j < i || eps[j] <= tol);
+              if (!use) h[(size_t)j * nk + q] = 0;
+            }
+          combine(c, nw, E, V12, nk, h, -1.0, X, V12, V12, true);
+        }
+        // ... then among the block members in index order, normalising each.
         for (int q = 0; q < nk; ++q) {
           const int i = todo[q0 + q];
           c128 *x = X + q * V12;
-          for (int pass = 0; pass < 2; ++pass) {
-            auto h = dots<double>(c, i, E, V12, 0, x, 0, V12, 1);
-            axpys<double>(c, i, E, V12, 0, h, x, 0, V12, 1, -1.0);
-          }
+          if (q > 0)
+            for (int pass = 0; pass < 2; ++pass) {
+              auto h = dots<double>(c, q, X, V12, 0, x, 0, V12, 1);
+              axpys<double>(c, q, X, V12, 0, h, x, 0, V12, 1, -1.0);
+            }
           auto nr = norms<double>(c, x, V12, 1);
           if (!(nr[0] > 0) || !std::isfinite(nr[0])) fail(LQ_ERR_NUMERIC, "RQI iterate collapsed");
-          scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, x, 0, E + i * V12, 0, V12, 1, false);
+          scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, x, 0, x, 0, V12, 1, false);
+          copy<double>(c, E + i * V12, x, V12);
         }
         S.t_ortho += now() - t0;
-        rebuild_from();
+        if (nw <= Nv) rebuild_from(sig);       // P holds every vector: put the new ones in
         t0 = now();
         rq_resid(std::vector<int>(todo.begin() + q0, todo.begin() + q0 + nk));
         S.t_rq += now() - t0;
+        if (verbose()) {
+          int itmax = 0;
+          for (int q = 0; q < nk; ++q) itmax = std::max(itmax, its[q]);
+          std::fprintf(stderr, "[lqmg]   sweep %d block at %zu: %d solves, max fgmres its %d, coarse its %d\n",
+                       S.sweeps + 1, q0, nk, itmax, c->coarse_iters);
+          std::fflush(stderr);
+        }
       }
       S.sweeps++;
-      if (c->p.rayleigh_ritz && nw > 1) {
-        double t0 = now();
-        rayleigh_ritz(c, E, nw, lam);
-        std::vector<int> all(nw);
-        for (int i = 0; i < nw; ++i) all[i] = i;
-        rq_resid(all);
-        S.t_rq += now() - t0;
-        rebuild_from();
+      if (c->p.rayleigh_ritz) {
+        // Rayleigh-Ritz among the unconverged vectors, after orthonormalising
+        // them against the locked (converged) ones; locked pairs stay as they are.
+        std::vector<int> U;
+        for (int i = 0; i < nw; ++i)
+          if (eps[i] > tol) U.push_back(i);
+        if (U.size() > 1) {
+          double t0 = now();
+          rayleigh_ritz_subset(c, E, nw, U, eps, tol, lam);
+          rq_resid(U);
+          S.t_rq += now() - t0;
+          if (nw <= Nv) rebuild_from({0.0});
+        }
       }
       done = wanted_done();
+      if (verbose()) {
+        int nconv = 0;
+        double emax = 0;
+        for (int i = 0; i < nw; ++i) {
+          nconv += eps[i] <= tol;
+          emax = std::max(emax, eps[i]);
+        }
+        std::fprintf(stderr, "[lqmg] rqi sweep %d: %d/%d converged, max eps %.3e, solves %d, fgmres its %d, "
+                     "t solve %.2fs ortho %.2fs rebuild %.2fs rq %.2fs\n", S.sweeps, nconv, nw, emax, S.solves,
+                     S.fgmres_iters, S.t_solve, S.t_ortho, S.t_rebuild, S.t_rq);
+        std::fflush(stderr);
+      }
     }
     // output: the n_eig smallest |lambda|, sorted by (|lambda|, lambda)
     std::vector<int> o(nw);
@@ -936,6 +1181,17 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     sync(c);
     if (stats) *stats = S;
     return done ? LQ_OK : LQ_WARN_NOCONV;
+  });
+}
+
+int lq_inner_products(lq_ctx *c, int nb, const lq_c128 *E, int nw, const lq_c128 *W, long long n, lq_c128 *out) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (nb < 1 || nb > 192 || nw < 1 || nw > 16 || n < 1 || !E || !W || !out)
+      fail(LQ_ERR_ARG, "lq_inner_products: bad arguments");
+    auto g = gram(c, nb, (const c128 *)E, n, nw, (const c128 *)W, n, n);
+    std::memcpy(out, g.data(), g.size() * sizeof(cd));
+    return LQ_OK;
   });
 }
 

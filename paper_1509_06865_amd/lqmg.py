@@ -22,7 +22,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
-            "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle"]
+            "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products"]
 
 
 class LQError(RuntimeError):
@@ -37,7 +37,8 @@ class _Params(C.Structure):
                 ("coarse_restarts", C.c_int), ("coarse_tol", C.c_double), ("fgmres_m", C.c_int),
                 ("fgmres_restarts", C.c_int), ("n_init", C.c_int), ("n_setup", C.c_int),
                 ("rqi_block", C.c_int), ("rqi_max_sweeps", C.c_int), ("rqi_solve_tol", C.c_double),
-                ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int)]
+                ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int), ("rqi_solve_restarts", C.c_int),
+                ("rqi_deflate", C.c_int)]
 
 
 class _SolveStats(C.Structure):
@@ -71,6 +72,8 @@ class MGParams:
     rqi_solve_tol: float | None = None
     rayleigh_ritz: int | None = None
     rqi_guard: int | None = None
+    rqi_solve_restarts: int | None = None
+    rqi_deflate: int | None = None
 
     def to_c(self, lib) -> _Params:
         p = _Params()
@@ -114,6 +117,7 @@ def load():
         "mg_coarse_apply": (i, [vp, i, dp, vp, vp]),
         "mg_smooth": (i, [vp, i, dp, vp, vp, i]),
         "mg_cycle": (i, [vp, i, dp, vp, vp]),
+        "lq_inner_products": (i, [vp, i, vp, i, vp, C.c_longlong, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -244,6 +248,16 @@ class Context:
         z = torch.empty_like(r)
         self._check(self.lib.mg_smooth(self.h, r.shape[0], _dbl(sigma), _ptr(r), _ptr(z), int(steps)))
         return z
+
+    def inner_products(self, E, W):
+        """<E_i, W_k> for device complex128 tensors E [nb, ...] and W [nw, ...]."""
+        import numpy as np
+        nb, nw = E.shape[0], W.shape[0]
+        n = E[0].numel()
+        out = np.empty((nb, nw), dtype=np.complex128)
+        self._check(self.lib.lq_inner_products(self.h, nb, _ptr(E), nw, _ptr(W), n,
+                                               C.c_void_p(out.ctypes.data)))
+        return out
 
     def cycle(self, sigma, r):
         z = torch.empty_like(r)

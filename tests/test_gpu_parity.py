@@ -76,6 +76,17 @@ def test_q_apply_many_rhs_chunks():
     assert relmax(y, ref) < 1e-13
 
 
+@pytest.mark.parametrize("nb,nw,n", [(1, 1, 7), (17, 5, 1000), (100, 16, 4096 * 3 + 29), (192, 16, 300)])
+def test_inner_products_match_numpy(nb, nw, n):
+    rng = np.random.default_rng(nb * 31 + nw)
+    E = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    W = rng.standard_normal((nw, n)) + 1j * rng.standard_normal((nw, n))
+    c = _ctx((4, 4, 4, 4), -1)
+    G = c.inner_products(dev(E), dev(W))
+    ref = E.conj() @ W.T
+    assert relmax(G, ref) < 1e-13
+
+
 # ------------------------------------------------------- multigrid pieces ----
 @pytest.fixture(scope="module", params=[0, 1], ids=["fp64", "mixed"])
 def hier(request):

@@ -38,7 +38,8 @@ def test_params_struct_matches_library_defaults():
     lib = lqmg.load()
     p = lqmg._Params()
     assert lib.lq_params_default(ctypes.byref(p)) == 0
-    assert p.rqi_block == 16 and p.fgmres_m == 10 and abs(p.rqi_solve_tol - 1e-8) < 1e-20
+    assert p.rqi_block == 16 and p.fgmres_m == 10 and abs(p.rqi_solve_tol - 1e-6) < 1e-20
+    assert p.rqi_deflate == 1 and p.rayleigh_ritz == 1
     assert lib.lq_params_default(None) == -1
 
 
