@@ -29,12 +29,14 @@ HBM_PEAK_GBS = 8000.0
 # Workloads: lattice, field, aggregation, Nv, N_eig, tolerance.  Masses come
 # from tests/golden/m0.json (written by tests/golden/make_m0.py).
 WORKLOADS = {
-    "large": dict(golden="large", agg=(4, 4, 4, 4), nv=24, n_eig=100, tol=1e-10, guard=8,
+    # guard bands reach past the near-degenerate momentum shell that the
+    # n_eig-th mode lies in (16^4: 12 + 96 modes; 32^3x64: 12 + 24 + 96)
+    "large": dict(golden="large", agg=(4, 4, 4, 4), nv=24, n_eig=100, tol=1e-10, guard=32,
                   params=dict(rqi_block=8, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=4,
-                              coarse_tol=0.05)),
-    "medium": dict(golden="medium", agg=(4, 4, 4, 4), nv=20, n_eig=50, tol=1e-10, guard=6,
+                              coarse_tol=0.15)),
+    "medium": dict(golden="medium", agg=(4, 4, 4, 4), nv=20, n_eig=50, tol=1e-10, guard=70,
                    params=dict(rqi_block=16, fgmres_m=10, n_setup=4, coarse_m=40, coarse_restarts=4,
-                               coarse_tol=0.05)),
+                               coarse_tol=0.15)),
     "small": dict(golden="tiny_periodic", agg=(2, 2, 2, 2), nv=8, n_eig=8, tol=1e-10, guard=4,
                   params=dict(rqi_block=4, fgmres_m=10, n_setup=4, coarse_m=128, coarse_restarts=2,
                               coarse_tol=1e-8)),
@@ -56,9 +58,12 @@ def device_gaussian(n, dims, seed, torch):
     V = int(np.prod(dims))
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    re = torch.randn((n, 12, V), generator=g, device="cuda", dtype=torch.float64)
-    im = torch.randn((n, 12, V), generator=g, device="cuda", dtype=torch.float64)
-    return torch.complex(re, im) / np.sqrt(2.0)
+    out = torch.empty((n, 12, V), dtype=torch.complex128, device="cuda")
+    view = torch.view_as_real(out)                    # [n, 12, V, 2] float64
+    for k in range(n):                                # one field at a time: small temporaries
+        view[k].normal_(generator=g)
+    out /= np.sqrt(2.0)
+    return out
 
 
 def time_q_apply(ctx, U, m0, x, reps, torch):
@@ -139,6 +144,7 @@ def main():
     V0 = device_gaussian(n_v0, dims, seed + 2, torch) if n_v0 > 0 else None
     prm = MGParams(precision=1, rqi_guard=wl["guard"], rayleigh_ritz=1, rqi_max_sweeps=args.max_sweeps,
                    **wl["params"])
+    torch.cuda.empty_cache()          # hand torch's cached temporaries back before the library allocates
     ctx = Context(dims, t_bc)
 
     # Dirac apply bandwidth (FP64 and FP32), device time per launch
@@ -151,6 +157,9 @@ def main():
     def step():
         ctx.mg_setup(U, m0, wl["agg"], tv0, prm)
         t_setup = time.time()
+        free, total = torch.cuda.mem_get_info()
+        log(f"after setup: device free {free / 2**30:.1f} GiB, torch reserved "
+            f"{torch.cuda.memory_reserved() / 2**30:.1f} GiB")
         lam, Vv, res, info = ctx.rqi_lowmodes(wl["n_eig"], wl["tol"], V0=V0)
         return lam, res, info, t_setup
 

@@ -29,19 +29,46 @@ __device__ inline double block_sum(double v, double *lds) {
   return r;
 }
 
-// Stage 1: partial[g*kDotGroup + i][k][chunk]
+// The last workgroup to finish (counted with an atomic after a fence) adds
+// the chunk partials of every (i, k) in chunk order, writes out[i][k] and
+// re-arms the counter: one launch, and the same order of additions every time.
+__device__ inline void finish_dots(int nv, int nrhs, int nchunks, const c128 *partial, c128 *out,
+                                   unsigned *counter) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned total = gridDim.x * gridDim.y * gridDim.z;
+    last = (atomicAdd(counter, 1u) == total - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int ik = threadIdx.x; ik < nv * nrhs; ik += blockDim.x) {
+    double re = 0, im = 0;
+    const volatile c128 *p = partial + (long long)ik * nchunks;
+    for (int c = 0; c < nchunks; ++c) { re += p[c].re; im += p[c].im; }
+    out[ik] = c128{re, im};
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+// Stage 1: partial[g*kDotGroup + i][k][chunk]; with out != nullptr the last
+// workgroup also performs the final reduction.
 template <typename T>
 __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx<T> *__restrict__ vbase,
                                                               long long vstride, long long rstride,
                                                               const cplx<T> *__restrict__ w, long long wstride,
                                                               long long n, c128 *__restrict__ partial,
-                                                              const int *__restrict__ active) {
+                                                              const int *__restrict__ active, c128 *out,
+                                                              unsigned *counter) {
   __shared__ double lds[kDotThreads / 64];
   const int chunk = blockIdx.x, k = blockIdx.y, grp = blockIdx.z;
   const int nchunks = gridDim.x, nrhs = gridDim.y;
   if (active && !active[k]) {
     if (threadIdx.x < kDotGroup && grp * kDotGroup + (int)threadIdx.x < nv)
       partial[((long long)(grp * kDotGroup + threadIdx.x) * nrhs + k) * nchunks + chunk] = c128{0, 0};
+    if (out != nullptr) finish_dots(nv, nrhs, nchunks, partial, out, counter);
     return;
   }
   const long long per = (n + nchunks - 1) / nchunks;
@@ -69,6 +96,7 @@ __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx
     double si = block_sum(im[i], lds);
     if (threadIdx.x == 0) partial[((long long)(i0 + i) * nrhs + k) * nchunks + chunk] = c128{sr, si};
   }
+  if (out != nullptr) finish_dots(nv, nrhs, nchunks, partial, out, counter);
 }
 
 // Stage 2: one wave per (i, k) sums the chunk partials in a fixed tree.
@@ -249,7 +277,7 @@ void launch_arnoldi_solve(int m, int nrhs, const c128 *H, const c128 *g, const i
 
 size_t dots_scratch_elems(int nv, int nrhs) {
   const int groups = (nv + kDotGroup - 1) / kDotGroup;
-  return (size_t)groups * kDotGroup * nrhs * kDotChunks;
+  return (size_t)groups * kDotGroup * nrhs * kDotChunks + 1;     // + counter slot
 }
 
 template <typename T>
@@ -261,11 +289,21 @@ void launch_dots(int nv, const cplx<T> *vbase, long long vstride, long long rstr
   if (nchunks > kDotChunks) nchunks = kDotChunks;
   if (nchunks < 1) nchunks = 1;
   const int groups = (nv + kDotGroup - 1) / kDotGroup;
+  // scratch[0] holds the completion counter (zero when the scratch is
+  // allocated, re-armed by every fused launch); the partial sums follow it
+  unsigned *counter = reinterpret_cast<unsigned *>(scratch);
+  c128 *partial = scratch + 1;
+  // The one-launch form (final sum by the last workgroup) serialises that sum
+  // on uncached loads and measured slower than the second launch, which
+  // reduces every (i, k) with its own wave; it stays available but is off.
+  const bool fused = false;
   hipLaunchKernelGGL((k_dots_partial<T>), dim3(nchunks, nrhs, groups), dim3(kDotThreads), 0, st, nv, vbase,
-                     vstride, rstride, w, wstride, n, scratch, active);
+                     vstride, rstride, w, wstride, n, partial, active, fused ? out : nullptr, counter);
   LQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_dots_final, dim3(nv * nrhs), dim3(64), 0, st, scratch, nchunks, out);
-  LQ_HIP(hipGetLastError());
+  if (!fused) {
+    hipLaunchKernelGGL(k_dots_final, dim3(nv * nrhs), dim3(64), 0, st, partial, nchunks, out);
+    LQ_HIP(hipGetLastError());
+  }
 }
 
 template <typename T>

@@ -49,6 +49,66 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T
   yout[((long long)k * cg.nA + A) * n2 + i] = acc;
 }
 
+// All right-hand sides of one coarse site per workgroup: each (2Nv)^2 block is
+// staged in LDS once and applied to every rhs, so the operator is read once
+// per call instead of once per rhs.  Thread t owns rows t % n2 .. for the rhs
+// t / n2, t / n2 + 256 / n2, ...
+template <typename T, int KCH>
+__global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
+                                                            const cplx<T> *__restrict__ xin,
+                                                            cplx<T> *__restrict__ yout, Shifts sig, bool g5form,
+                                                            int nrhs) {
+  __shared__ cplx<T> blk[64 * 64];
+  __shared__ cplx<T> xs[KCH][64];
+  const int A = blockIdx.x;
+  const int n2 = cg.n2;
+  const long long bs = (long long)n2 * n2;
+  int nb[9];
+  nb[0] = A;
+  for (int mu = 0; mu < 4; ++mu) { nb[1 + mu] = cnbr(cg, A, mu, 1); nb[5 + mu] = cnbr(cg, A, mu, -1); }
+  const int t = threadIdx.x;
+  const int rows_per = n2;                          // threads per rhs
+  const int rhs_slots = 256 / rows_per;             // rhs handled at once
+  const int i = t % rows_per, ks = t / rows_per;
+  for (int k0 = 0; k0 < nrhs; k0 += KCH) {
+    const int kc = (nrhs - k0 < KCH) ? nrhs - k0 : KCH;
+    cplx<T> acc[(KCH + 3) / 4 > 0 ? (KCH + 3) / 4 : 1];
+    const int nacc = (kc + rhs_slots - 1) / rhs_slots;
+    for (int a = 0; a < (int)(sizeof(acc) / sizeof(acc[0])); ++a) acc[a] = mk<T>(0, 0);
+    for (int d = 0; d < 9; ++d) {
+      __syncthreads();
+      const cplx<T> *M = (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
+      for (int e = t; e < n2 * n2; e += 256) blk[e] = M[e];
+      for (int e = t; e < kc * n2; e += 256) {
+        const int k = e / n2, j = e - k * n2;
+        xs[k][j] = xin[((long long)(k0 + k) * cg.nA + nb[d]) * n2 + j];
+      }
+      __syncthreads();
+      if (i < n2)
+        for (int a = 0; a < nacc; ++a) {
+          const int k = ks + a * rhs_slots;
+          if (k >= kc) break;
+          cplx<T> s = mk<T>(0, 0);
+          if (d < 5)
+            for (int j = 0; j < n2; ++j) s = s + blk[i * n2 + j] * xs[k][j];
+          else
+            for (int j = 0; j < n2; ++j) s = s + cmul_conj(blk[j * n2 + i], xs[k][j]);
+          acc[a] = acc[a] + s;
+        }
+    }
+    __syncthreads();
+    if (i < n2 && ks < rhs_slots)
+      for (int a = 0; a < nacc; ++a) {
+        const int k = ks + a * rhs_slots;
+        if (k >= kc) break;
+        const long long off = ((long long)(k0 + k) * cg.nA + A) * n2 + i;
+        cplx<T> v = acc[a] - (T)sig.s[k0 + k] * xin[off];
+        if (g5form && i >= n2 / 2) v = -v;
+        yout[off] = v;
+      }
+  }
+}
+
 template <typename T>
 __global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T> *__restrict__ y, long long n) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,7 +123,16 @@ __global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T
 template <typename T>
 void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig,
                          int nrhs, bool g5form, hipStream_t st) {
-  hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, g5form);
+  // Few coarse sites (< 1024): one wave per (site, rhs) keeps the GPU busy;
+  // many sites: one workgroup per site, operator blocks read once for all rhs.
+  if (nrhs >= 4 && cg.n2 <= 64 && cg.nA >= 1024) {
+    // FP32: all 16 rhs per pass; FP64 (twice the LDS per element): 8 per pass
+    constexpr int KCH = sizeof(T) == 4 ? 16 : 8;
+    hipLaunchKernelGGL((k_coarse_apply_multi<T, KCH>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, g5form,
+                       nrhs);
+  } else {
+    hipLaunchKernelGGL((k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, g5form);
+  }
   LQ_HIP(hipGetLastError());
 }
 

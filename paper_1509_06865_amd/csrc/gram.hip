@@ -5,9 +5,12 @@
 // Ritz and Galerkin-correction products of the eigensolver.
 //
 // Gram kernel: split-K.  A workgroup owns a contiguous range of vector
-// elements; it stages the W tile (16 x 64 elements) in LDS and its four waves
-// run 16x16x4 FP64 MFMAs over 16-row tiles of E.  A complex inner product is
-// four real products: Re C = Er.Wr + Ei.Wi, Im C = Er.Wi - Ei.Wr.  Partial
+// elements and has one wave per 16-row tile of E, so every wave does the same
+// work; the W tile sits in LDS and is shared by all waves.  A complex inner
+// product needs Re C = Er.Wr + Ei.Wi and Im C = Er.Wi - Ei.Wr.  Eight W
+// vectors fill one 16-column MFMA operand as [Wr | Wi] and [Wi | -Wr]: two
+// 16x16x4 FP64 MFMAs (A = Er, then A = Ei) leave [Re C | Im C] in one
+// accumulator, so no MFMA work is spent on padding when nw <= 8.  Partial
 // tiles go to scratch and a second kernel adds the chunks in a fixed order.
 #include "lq_kernels.h"
 
@@ -16,102 +19,129 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kGramTile = 64;       // elements per LDS tile
-constexpr int kGramMaxMT = 10;      // up to 160 basis vectors
+constexpr int kGramTile = 128;      // elements per LDS tile
+constexpr int kGramMaxMT = 12;      // up to 192 basis vectors, one wave per 16-row tile
+constexpr long long kGramMaxChunks = 2048;
 
-__global__ void __launch_bounds__(256) k_gram(int nb, const c128 *__restrict__ E, long long estride, int nw,
-                                              const c128 *__restrict__ W, long long wstride, long long n,
-                                              long long per_chunk, c128 *__restrict__ partial) {
-  __shared__ c128 wt[16][kGramTile];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+template <int NCG>                   // column groups of 8 W vectors
+__global__ void __launch_bounds__(64 * kGramMaxMT) k_gram(int nb, const c128 *__restrict__ E, long long estride,
+                                                          int nw, const c128 *__restrict__ W, long long wstride,
+                                                          long long n, long long per_chunk,
+                                                          double *__restrict__ partial) {
+  __shared__ c128 wt[8 * NCG][kGramTile + 4];     // +4: rows start on different LDS banks
+  const int lane = threadIdx.x & 63, mt = threadIdx.x >> 6;
   const long long lo = (long long)blockIdx.x * per_chunk;
   const long long hi = (lo + per_chunk < n) ? lo + per_chunk : n;
-  const int nmt = (nb + 15) / 16;
-  v4d acc_re[3], acc_im[3];          // up to 3 M-tiles per wave (nb <= 192)
+  v4d acc[NCG];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    acc_re[q] = v4d{0, 0, 0, 0};
-    acc_im[q] = v4d{0, 0, 0, 0};
-  }
+  for (int g = 0; g < NCG; ++g) acc[g] = v4d{0, 0, 0, 0};
+  // A operand: lane l holds A[l % 16][l / 16]: row = basis vector, k = element
+  // B operand: lane l holds B[l / 16][l % 16]: k = element, column = (vector, part)
+  // Rows past nb read row nb - 1 and their results are dropped; elements past
+  // the chunk read its last element and meet zeros in the W tile.  The loads
+  // are then unconditional and a wave keeps eight of them in flight.
   const int row = lane & 15, kk = lane >> 4;
+  const int i = mt * 16 + row;
+  const c128 *Ei = E + (long long)(i < nb ? i : nb - 1) * estride;
+  const int wcol = lane & 7;
+  const bool upper = (lane & 8) != 0;
   for (long long t0 = lo; t0 < hi; t0 += kGramTile) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 16 * kGramTile; idx += 256) {
+    for (int idx = threadIdx.x; idx < 8 * NCG * kGramTile; idx += blockDim.x) {
       const int k = idx / kGramTile, e = idx - k * kGramTile;
-      const long long g = t0 + e;
-      wt[k][e] = (k < nw && g < hi) ? W[(long long)k * wstride + g] : c128{0, 0};
+      const long long gi = t0 + e;
+      wt[k][e] = (k < nw && gi < hi) ? W[(long long)k * wstride + gi] : c128{0, 0};
     }
     __syncthreads();
+    const long long last = hi - 1 - t0;
+    for (int s0 = 0; s0 < kGramTile / 4; s0 += 8) {
+      c128 a[8];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int mt = wave + 4 * q;
-      if (mt >= nmt) break;
-      const int i = mt * 16 + row;
-      const c128 *Ei = E + (long long)i * estride;
-#pragma unroll 4
-      for (int s = 0; s < kGramTile / 4; ++s) {
-        const int e = 4 * s + kk;
-        const long long g = t0 + e;
-        c128 a = (i < nb && g < hi) ? Ei[g] : c128{0, 0};
-        const c128 b = wt[row][e];          // B[k = e][col = row] -> W_row[e]
-        acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, acc_re[q], 0, 0, 0);
-        acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, acc_re[q], 0, 0, 0);
-        acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, acc_im[q], 0, 0, 0);
-        acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.re, acc_im[q], 0, 0, 0);
+      for (int u = 0; u < 8; ++u) {
+        const long long e = 4 * (s0 + u) + kk;
+        a[u] = Ei[t0 + (e < last ? e : last)];
+      }
+      // the scheduler otherwise sinks each load to its MFMA, one load in flight
+#pragma unroll
+      for (int u = 0; u < 8; ++u) asm volatile("" ::"v"(a[u].re), "v"(a[u].im));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = 4 * (s0 + u) + kk;
+#pragma unroll
+        for (int g = 0; g < NCG; ++g) {
+          const c128 w = wt[8 * g + wcol][e];
+          const double b1 = upper ? w.im : w.re;
+          const double b2 = upper ? -w.re : w.im;
+          acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].re, b1, acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].im, b2, acc[g], 0, 0, 0);
+        }
       }
     }
   }
-  // 16x16x4 FP64 MFMA result: register j of lane l holds D[4 j + l / 16][l % 16]
+  // 16x16x4 FP64 MFMA result: register j of lane l holds D[4 j + l / 16][l % 16];
+  // column c < 8 is Re C[., 8g + c], column c >= 8 is Im C[., 8g + c - 8]
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int mt = wave + 4 * q;
-    if (mt >= nmt) break;
-    const int col = lane & 15;
+  for (int g = 0; g < NCG; ++g) {
+    const int k = 8 * g + wcol;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = 4 * j + (lane >> 4);
-      const int i = mt * 16 + r;
-      if (i < nb && col < nw)
-        partial[((long long)blockIdx.x * nb + i) * 16 + col] = c128{acc_re[q][j], acc_im[q][j]};
+      const int r = mt * 16 + 4 * j + (lane >> 4);
+      if (r < nb && k < nw) partial[(((long long)blockIdx.x * nb + r) * 16 + k) * 2 + (upper ? 1 : 0)] = acc[g][j];
     }
   }
 }
 
 // out[i][k] = sum over chunks of partial[chunk][i][k], fixed order
-__global__ void k_gram_final(int nb, int nw, int nchunks, const c128 *__restrict__ partial, c128 *__restrict__ out) {
+__global__ void k_gram_final(int nb, int nw, int nchunks, const double *__restrict__ partial, c128 *__restrict__ out) {
   const int ik = blockIdx.x * blockDim.x + threadIdx.x;
   if (ik >= nb * nw) return;
   const int i = ik / nw, k = ik - i * nw;
   double re = 0, im = 0;
   for (int c = 0; c < nchunks; ++c) {
-    const c128 v = partial[((long long)c * nb + i) * 16 + k];
-    re += v.re;
-    im += v.im;
+    const double *v = partial + (((long long)c * nb + i) * 16 + k) * 2;
+    re += v[0];
+    im += v[1];
   }
   out[ik] = c128{re, im};
 }
 
-// U_k[e] = (U_k[e] if acc) + sum_i Y[i][k] E_i[e], one thread per element
+// U_k[e] = (U_k[e] if acc) + sum_i Y[i][k] E_i[e], one thread per element.
+// The coefficients are the same for the whole wave (scalar loads); E is read
+// in batches of eight basis vectors with all loads in flight.
+template <int NWT, bool EXACT>       // EXACT: nw == NWT, the column loop has no tests
 __global__ void __launch_bounds__(256) k_combine(int nb, const c128 *__restrict__ E, long long estride, int nw,
                                                  const c128 *__restrict__ Y, c128 *__restrict__ U,
                                                  long long ustride, long long n, bool acc) {
-  extern __shared__ c128 ys[];        // [nb][nw]
-  for (int idx = threadIdx.x; idx < nb * nw; idx += blockDim.x) ys[idx] = Y[idx];
-  __syncthreads();
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  c128 u[16];
+  c128 u[NWT];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) u[k] = c128{0, 0};
-  for (int i = 0; i < nb; ++i) {
+  for (int k = 0; k < NWT; ++k) u[k] = c128{0, 0};
+  const int nfull = nb & ~7;
+  for (int i0 = 0; i0 < nfull; i0 += 8) {
+    c128 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = E[(long long)(i0 + q) * estride + e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) asm volatile("" ::"v"(v[q].re), "v"(v[q].im));
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const c128 *y = Y + (long long)(i0 + q) * nw;
+#pragma unroll
+      for (int k = 0; k < NWT; ++k)
+        if (EXACT || k < nw) u[k] = u[k] + y[k] * v[q];
+    }
+  }
+  for (int i = nfull; i < nb; ++i) {
     const c128 v = E[(long long)i * estride + e];
+    const c128 *y = Y + (long long)i * nw;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (k < nw) u[k] = u[k] + ys[i * nw + k] * v;
+    for (int k = 0; k < NWT; ++k)
+      if (EXACT || k < nw) u[k] = u[k] + y[k] * v;
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (k < nw) {
+  for (int k = 0; k < NWT; ++k)
+    if (EXACT || k < nw) {
       c128 *p = U + (long long)k * ustride + e;
       *p = acc ? *p + u[k] : u[k];
     }
@@ -121,24 +151,31 @@ __global__ void __launch_bounds__(256) k_combine(int nb, const c128 *__restrict_
 
 size_t gram_scratch_elems(long long n) {
   (void)n;
-  return (size_t)1024 * 192 * 16;
+  return (size_t)kGramMaxChunks * 192 * 16;
 }
 
 void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W, long long wstride, long long n,
                  c128 *out, c128 *scratch, hipStream_t st) {
   if (nb <= 0 || nw <= 0) return;
-  if (nb > 192 || nw > 16) throw HipError(hipErrorInvalidValue, "launch_gram: nb <= 192 and nw <= 16", __FILE__, __LINE__);
-  long long nchunks = (n + 4095) / 4096;
-  if (nchunks > 1024) nchunks = 1024;
+  if (nb > 16 * kGramMaxMT || nw > 16)
+    throw HipError(hipErrorInvalidValue, "launch_gram: nb <= 192 and nw <= 16", __FILE__, __LINE__);
+  long long nchunks = (n + 8191) / 8192;
+  if (nchunks > kGramMaxChunks) nchunks = kGramMaxChunks;
   if (nchunks < 1) nchunks = 1;
   long long per = (n + nchunks - 1) / nchunks;
   per = ((per + kGramTile - 1) / kGramTile) * kGramTile;
   nchunks = (n + per - 1) / per;
-  hipLaunchKernelGGL(k_gram, dim3((unsigned)nchunks), dim3(256), 0, st, nb, E, estride, nw, W, wstride, n, per,
-                     scratch);
+  const int nmt = (nb + 15) / 16;
+  double *part = reinterpret_cast<double *>(scratch);
+  if (nw <= 8)
+    hipLaunchKernelGGL((k_gram<1>), dim3((unsigned)nchunks), dim3(64 * nmt), 0, st, nb, E, estride, nw, W, wstride,
+                       n, per, part);
+  else
+    hipLaunchKernelGGL((k_gram<2>), dim3((unsigned)nchunks), dim3(64 * nmt), 0, st, nb, E, estride, nw, W, wstride,
+                       n, per, part);
   LQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_gram_final, dim3(blocks_for((long long)nb * nw, 256)), dim3(256), 0, st, nb, nw,
-                     (int)nchunks, scratch, out);
+                     (int)nchunks, part, out);
   LQ_HIP(hipGetLastError());
 }
 
@@ -146,9 +183,15 @@ void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128
                     long long n, bool accumulate, hipStream_t st) {
   if (nb <= 0 || nw <= 0) return;
   if (nb > 192 || nw > 16) throw HipError(hipErrorInvalidValue, "launch_combine: nb <= 192 and nw <= 16", __FILE__, __LINE__);
-  const size_t lds = (size_t)nb * nw * sizeof(c128);
-  hipLaunchKernelGGL(k_combine, dim3(blocks_for(n, 256)), dim3(256), lds, st, nb, E, estride, nw, Y, U, ustride, n,
-                     accumulate);
+  const dim3 grid(blocks_for(n, 256)), block(256);
+  if (nw == 8)
+    hipLaunchKernelGGL((k_combine<8, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+  else if (nw == 16)
+    hipLaunchKernelGGL((k_combine<16, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+  else if (nw < 8)
+    hipLaunchKernelGGL((k_combine<8, false>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+  else
+    hipLaunchKernelGGL((k_combine<16, false>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
   LQ_HIP(hipGetLastError());
 }
 

@@ -49,8 +49,13 @@ template <typename T> struct DevBuf {
     if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
-      fail(LQ_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      size_t fr = 0, tot = 0;
+      (void)hipMemGetInfo(&fr, &tot);
+      fail(LQ_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed (" +
+                           std::to_string(fr >> 20) + " MiB free of " + std::to_string(tot >> 20) + ")");
     }
+    // new buffers start zeroed (reduction counters rely on it)
+    if (hipMemset(p, 0, count * sizeof(T)) != hipSuccess) fail(LQ_ERR_HIP, "hipMemset failed");
     n = count;
     return p;
   }
@@ -145,7 +150,6 @@ struct lq_ctx {
   DevBuf<c64> parts32, pc32;
   DevBuf<c128> eig;                 // RQI vectors, blocked FP64 [n][12][V]
   DevBuf<c128> sel;                 // vectors that build P [Nv][12][V]
-  DevBuf<c128> rr_gather;
   DevBuf<c128> defl_tmp, defl_u, defl_r;   // Galerkin correction work           // Rayleigh-Ritz: gathered unconverged vectors
   DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
   int coarse_iters = 0;
@@ -440,7 +444,7 @@ template <typename T> void build_coarse(lq_ctx *c, DevBuf<cplx<T>> &parts, DevBu
   auto &d = mgd<T>(c);
   const int Nv = c->Nv, n2 = 2 * Nv, nA = c->cg.nA;
   const long long V12 = 12LL * c->g.V;
-  const int C = std::min(Nv, 8);
+  const int C = std::min(Nv, 4);           // columns per pass: 5*C split-hop fields in flight
   cplx<T> *pa = parts.get((size_t)C * 5 * V12);
   cplx<T> *pcb = pc.get((size_t)C * 5 * nA * n2);
   cplx<T> *Qc = d.Qc.get((size_t)nA * 5 * n2 * n2);
@@ -569,42 +573,121 @@ void jacobi_eigh(int n, std::vector<cd> &A, std::vector<cd> &Vm) {
 // E <- E C ordered by (|w|, w); lam receives w.
 void rayleigh_ritz(lq_ctx *c, const c128 *E, int n, std::vector<double> &lam, const std::vector<c128 *> &dst);
 
-// Rayleigh-Ritz restricted to the vectors U of E (nw fields): they are first
-// made orthonormal to the locked vectors (eps <= tol) and to each other
-// (Gram-Schmidt twice, index order), gathered, rotated to Ritz vectors and
-// written back to their slots in order of increasing |Ritz value|.
-void rayleigh_ritz_subset(lq_ctx *c, c128 *E, int nw, const std::vector<int> &U, const std::vector<double> &eps,
-                          double tol, std::vector<double> &lam) {
+// Reorder the n fields of E in place so that slot p receives old slot order[p]
+// (cycle following with one spare field).
+void permute_fields(lq_ctx *c, c128 *E, const std::vector<int> &order, c128 *spare) {
   const long long V12 = 12LL * c->g.V;
-  const int n = (int)U.size();
-  c128 *G = c->rr_gather.get((size_t)n * V12);
-  for (int q = 0; q < n; ++q) copy<double>(c, G + q * V12, E + U[q] * V12, V12);
-  std::vector<int> locked;
-  for (int i = 0; i < nw; ++i)
-    if (eps[i] <= tol) locked.push_back(i);
-  for (int q = 0; q < n; ++q) {
-    c128 *x = G + q * V12;
-    for (int pass = 0; pass < 2; ++pass) {
-      if (!locked.empty()) {
-        auto h = dots<double>(c, nw, E, V12, 0, x, 0, V12, 1);
-        std::vector<cd> hl((size_t)nw, cd(0));
-        for (int j : locked) hl[j] = h[j];
-        axpys<double>(c, nw, E, V12, 0, hl, x, 0, V12, 1, -1.0);
-      }
-      if (q > 0) {
-        auto h = dots<double>(c, q, G, V12, 0, x, 0, V12, 1);
-        axpys<double>(c, q, G, V12, 0, h, x, 0, V12, 1, -1.0);
-      }
+  const int n = (int)order.size();
+  std::vector<char> done(n, 0);
+  for (int p = 0; p < n; ++p) {
+    if (done[p] || order[p] == p) { done[p] = 1; continue; }
+    copy<double>(c, spare, E + p * V12, V12);
+    int cur = p;
+    while (true) {
+      const int src = order[cur];
+      done[cur] = 1;
+      if (src == p) { copy<double>(c, E + cur * V12, spare, V12); break; }
+      copy<double>(c, E + cur * V12, E + src * V12, V12);
+      cur = src;
     }
-    auto nr = norms<double>(c, x, V12, 1);
-    if (!(nr[0] > 0) || !std::isfinite(nr[0])) fail(LQ_ERR_NUMERIC, "vector collapsed before Rayleigh-Ritz");
-    scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, x, 0, x, 0, V12, 1, false);
   }
-  std::vector<double> w(n);
-  std::vector<c128 *> dst(n);
-  for (int q = 0; q < n; ++q) dst[q] = E + U[q] * V12;
-  rayleigh_ritz(c, G, n, w, dst);
-  for (int q = 0; q < n; ++q) lam[U[q]] = w[q];
+  sync(c);
+}
+
+// Rayleigh-Ritz on the trailing fields E[L..n) (the unconverged vectors; the
+// converged ones sit in E[0..L)).  The trailing block is first projected
+// against E[0..L) (block Gram-Schmidt, twice); then with H = E_U^dag Q E_U and
+// G = E_U^dag E_U the pencil (H, G) is reduced by G = L L^dag to
+// L^-1 H L^-dag = Z w Z^dag, and the Ritz vectors E_U L^-dag Z, ordered by
+// (|w|, w), replace E_U.  spill[j] is room for Ritz vector j (n - L fields,
+// none overlapping E).
+void rayleigh_ritz_tail(lq_ctx *c, c128 *E, int n, int L, std::vector<double> &lam,
+                        const std::vector<c128 *> &spill) {
+  const long long V12 = 12LL * c->g.V;
+  const int m = n - L;
+  c128 *EU = E + (long long)L * V12;
+  for (int pass = 0; pass < 2 && L > 0; ++pass)
+    for (int j0 = 0; j0 < m; j0 += kMaxRhs) {
+      const int nk = std::min(kMaxRhs, m - j0);
+      auto h = gram(c, L, E, V12, nk, EU + j0 * V12, V12, V12);
+      combine(c, L, E, V12, nk, h, -1.0, EU + j0 * V12, V12, V12, true);
+    }
+  std::vector<cd> H((size_t)m * m), G((size_t)m * m);
+  c128 *QE = c->tmpA.get((size_t)kMaxRhs * V12);
+  Shifts z = shifts_of(nullptr, 0);
+  for (int j0 = 0; j0 < m; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, m - j0);
+    launch_wilson<double>(c->g, c->U64.p, EU + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+    auto a = gram(c, m, EU, V12, nk, QE, V12, V12);
+    auto g = gram(c, m, EU, V12, nk, EU + j0 * V12, V12, V12);
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < nk; ++k) {
+        H[(size_t)i * m + j0 + k] = a[(size_t)i * nk + k];
+        G[(size_t)i * m + j0 + k] = g[(size_t)i * nk + k];
+      }
+  }
+  // Cholesky G = Lc Lc^dag (lower), then M = Lc^-1 H Lc^-dag
+  std::vector<cd> Lc((size_t)m * m, cd(0));
+  for (int j = 0; j < m; ++j) {
+    double d = G[(size_t)j * m + j].real();
+    for (int k = 0; k < j; ++k) d -= std::norm(Lc[(size_t)j * m + k]);
+    if (!(d > 1e-14 * std::fabs(G[(size_t)j * m + j].real()))) fail(LQ_ERR_NUMERIC, "Rayleigh-Ritz basis is singular");
+    const double ljj = std::sqrt(d);
+    Lc[(size_t)j * m + j] = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      cd v = G[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * m + k] * std::conj(Lc[(size_t)j * m + k]);
+      Lc[(size_t)i * m + j] = v / ljj;
+    }
+  }
+  auto lower_solve = [&](std::vector<cd> &B, int ncol) {         // B <- Lc^-1 B, B [m][ncol]
+    for (int col = 0; col < ncol; ++col)
+      for (int i = 0; i < m; ++i) {
+        cd v = B[(size_t)i * ncol + col];
+        for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * m + k] * B[(size_t)k * ncol + col];
+        B[(size_t)i * ncol + col] = v / Lc[(size_t)i * m + i];
+      }
+  };
+  std::vector<cd> T = H;                  // T = Lc^-1 H
+  lower_solve(T, m);
+  std::vector<cd> Tt((size_t)m * m);      // Tt = (Lc^-1 T^dag) = Lc^-1 H Lc^-dag (H Hermitian)
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) Tt[(size_t)i * m + j] = std::conj(T[(size_t)j * m + i]);
+  lower_solve(Tt, m);
+  for (int i = 0; i < m; ++i)
+    for (int j = i; j < m; ++j) {
+      const cd h = 0.5 * (Tt[(size_t)i * m + j] + std::conj(Tt[(size_t)j * m + i]));
+      Tt[(size_t)i * m + j] = h;
+      Tt[(size_t)j * m + i] = std::conj(h);
+    }
+  std::vector<cd> Zm;
+  jacobi_eigh(m, Tt, Zm);
+  // Y = Lc^-dag Z: back substitution with Lc^dag (upper)
+  std::vector<cd> Y = Zm;
+  for (int col = 0; col < m; ++col)
+    for (int i = m - 1; i >= 0; --i) {
+      cd v = Y[(size_t)i * m + col];
+      for (int k = i + 1; k < m; ++k) v -= std::conj(Lc[(size_t)k * m + i]) * Y[(size_t)k * m + col];
+      Y[(size_t)i * m + col] = v / Lc[(size_t)i * m + i];
+    }
+  std::vector<int> o(m);
+  for (int i = 0; i < m; ++i) o[i] = i;
+  std::sort(o.begin(), o.end(), [&](int a, int b) {
+    const double wa = Tt[(size_t)a * m + a].real(), wb = Tt[(size_t)b * m + b].real();
+    if (std::fabs(wa) != std::fabs(wb)) return std::fabs(wa) < std::fabs(wb);
+    return wa < wb;
+  });
+  c128 *chunk = c->tmpB.get((size_t)kMaxRhs * V12);
+  for (int j0 = 0; j0 < m; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, m - j0);
+    std::vector<cd> h((size_t)m * nk);
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < nk; ++k) h[(size_t)i * nk + k] = Y[(size_t)i * m + o[j0 + k]];
+    combine(c, m, EU, V12, nk, h, 1.0, chunk, V12, V12, false);
+    for (int k = 0; k < nk; ++k) copy<double>(c, spill[j0 + k], chunk + k * V12, V12);
+  }
+  for (int j = 0; j < m; ++j) copy<double>(c, EU + (long long)j * V12, spill[j], V12);
+  for (int j = 0; j < m; ++j) lam[L + j] = Tt[(size_t)o[j] * m + o[j]].real();
   sync(c);
 }
 
@@ -945,8 +1028,10 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
       orthonormalise(c, W, n_tv);
       rebuild(c, W);
       if (verbose()) {
-        std::fprintf(stderr, "[lqmg] setup pass %d/%d done, coarse its so far %d\n", it + 1, p.n_setup,
-                     c->coarse_iters);
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        std::fprintf(stderr, "[lqmg] setup pass %d/%d done, coarse its so far %d, device memory free %zu MiB\n",
+                     it + 1, p.n_setup, c->coarse_iters, fr >> 20);
         std::fflush(stderr);
       }
     }
@@ -1141,12 +1226,34 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
       if (c->p.rayleigh_ritz) {
         // Rayleigh-Ritz among the unconverged vectors, after orthonormalising
         // them against the locked (converged) ones; locked pairs stay as they are.
-        std::vector<int> U;
+        // The converged vectors are first moved to the front slots.
+        std::vector<int> order;
         for (int i = 0; i < nw; ++i)
-          if (eps[i] > tol) U.push_back(i);
-        if (U.size() > 1) {
+          if (eps[i] <= tol) order.push_back(i);
+        const int L = (int)order.size();
+        for (int i = 0; i < nw; ++i)
+          if (eps[i] > tol) order.push_back(i);
+        if (nw - L > 1) {
           double t0 = now();
-          rayleigh_ritz_subset(c, E, nw, U, eps, tol, lam);
+          permute_fields(c, E, order, c->tmpB.get((size_t)kMaxRhs * V12));
+          std::vector<double> l2(nw), e2(nw);
+          for (int p = 0; p < nw; ++p) { l2[p] = lam[order[p]]; e2[p] = eps[order[p]]; }
+          lam = l2;
+          eps = e2;
+          // the FGMRES basis vectors (V, then Z) are idle here and hold the
+          // rotated vectors; only if they are too few is more memory taken
+          std::vector<c128 *> spill;
+          const size_t nV = c->fine_kw.V.n / V12, nZ = c->fine_kw.Z.n / V12;
+          if (nV + nZ >= (size_t)(nw - L)) {
+            for (int j = 0; j < nw - L; ++j)
+              spill.push_back((size_t)j < nV ? c->fine_kw.V.p + j * V12 : c->fine_kw.Z.p + (j - nV) * V12);
+          } else {
+            c128 *sp = c->fine_kw.V.get((size_t)(nw - L) * V12);
+            for (int j = 0; j < nw - L; ++j) spill.push_back(sp + j * V12);
+          }
+          rayleigh_ritz_tail(c, E, nw, L, lam, spill);
+          std::vector<int> U;
+          for (int i = L; i < nw; ++i) U.push_back(i);
           rq_resid(U);
           S.t_rq += now() - t0;
           if (nw <= Nv) rebuild_from({0.0});

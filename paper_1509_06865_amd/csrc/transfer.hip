@@ -17,73 +17,104 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
-// c[j][A][h*Nv + k] = sum over the aggregate's sites of conj(P_k) . f_j on half h
-template <typename T>
+// c[j][A][h*Nv + k] = sum over the aggregate's sites of conj(P_k) . f_j on half h.
+// One workgroup per (aggregate, group of R fields): each P_k value is loaded
+// once for the R fields held in registers.
+template <typename T, int R>
 __global__ void __launch_bounds__(256) k_restrict(Geom g, const cplx<T> *__restrict__ P, int Nv,
-                                                  const cplx<T> *__restrict__ f, long long fstride,
+                                                  const cplx<T> *__restrict__ f, long long fstride, int nf,
                                                   cplx<T> *__restrict__ c) {
-  __shared__ double part[4][64][4];     // [wave][k][h re, h im]
-  const int A = blockIdx.x, j = blockIdx.y;
+  __shared__ double part[4][32][R][4];     // [wave][k][field][h re, h im]
+  const int A = blockIdx.x, j0 = blockIdx.y * R;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
   const bool active = t < g.bvol;
   const int s = A * g.bvol + (active ? t : 0);
-  cplx<T> fv[12];
+  cplx<T> fv[R][12];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) fv[i] = active ? f[j * fstride + (long long)i * g.V + s] : mk<T>(0, 0);
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      fv[r][i] = (active && j0 + r < nf) ? f[(j0 + r) * fstride + (long long)i * g.V + s] : mk<T>(0, 0);
   for (int k = 0; k < Nv; ++k) {
-    double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
-    if (active) {
-      const cplx<T> *Pk = P + (long long)k * 12 * g.V;
+    cplx<T> pv[12];
+    const cplx<T> *Pk = P + (long long)k * 12 * g.V;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) pv[i] = active ? Pk[(long long)i * g.V + s] : mk<T>(0, 0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
-        const cplx<T> pv = Pk[(long long)i * g.V + s];
-        const double re = (double)pv.re * fv[i].re + (double)pv.im * fv[i].im;
-        const double im = (double)pv.re * fv[i].im - (double)pv.im * fv[i].re;
+        const double re = (double)pv[i].re * fv[r][i].re + (double)pv[i].im * fv[r][i].im;
+        const double im = (double)pv[i].re * fv[r][i].im - (double)pv[i].im * fv[r][i].re;
         if (i < 6) { a0r += re; a0i += im; } else { a1r += re; a1i += im; }
       }
+      a0r = wsum(a0r); a0i = wsum(a0i); a1r = wsum(a1r); a1i = wsum(a1i);
+      if (lane == 0) {
+        part[wave][k][r][0] = a0r; part[wave][k][r][1] = a0i;
+        part[wave][k][r][2] = a1r; part[wave][k][r][3] = a1i;
+      }
     }
-    a0r = wsum(a0r); a0i = wsum(a0i); a1r = wsum(a1r); a1i = wsum(a1i);
-    if (lane == 0) { part[wave][k][0] = a0r; part[wave][k][1] = a0i; part[wave][k][2] = a1r; part[wave][k][3] = a1i; }
   }
   __syncthreads();
   const int n2 = 2 * Nv;
-  if (t < n2) {
-    const int h = t / Nv, k = t - h * Nv;
+  for (int q = t; q < R * n2; q += blockDim.x) {
+    const int r = q / n2, e = q - r * n2;
+    if (j0 + r >= nf) continue;
+    const int h = e / Nv, k = e - h * Nv;
     double re = 0, im = 0;
-    for (int w = 0; w < nw; ++w) { re += part[w][k][2 * h]; im += part[w][k][2 * h + 1]; }
-    c[((long long)j * g.nblk + A) * n2 + t] = mk<T>((T)re, (T)im);
+    for (int w = 0; w < nw; ++w) { re += part[w][k][r][2 * h]; im += part[w][k][r][2 * h + 1]; }
+    c[((long long)(j0 + r) * g.nblk + A) * n2 + e] = mk<T>((T)re, (T)im);
   }
 }
 
-// f_j(x) (+)= sum_k P_k(x) c_j[A][h(x) Nv + k]
-template <typename T>
+// f_j(x) (+)= sum_k P_k(x) c_j[A][h(x) Nv + k], R fields per workgroup
+template <typename T, int R>
 __global__ void __launch_bounds__(256) k_prolong(Geom g, const cplx<T> *__restrict__ P, int Nv,
                                                  const cplx<T> *__restrict__ c, cplx<T> *__restrict__ f,
-                                                 long long fstride, bool acc) {
-  __shared__ cplx<T> cs[64];
-  const int A = blockIdx.x, j = blockIdx.y;
+                                                 long long fstride, int nf, bool acc) {
+  __shared__ cplx<T> cs[R][64];
+  const int A = blockIdx.x, j0 = blockIdx.y * R;
   const int t = threadIdx.x;
   const int n2 = 2 * Nv;
-  if (t < n2) cs[t] = c[((long long)j * g.nblk + A) * n2 + t];
+  for (int q = t; q < R * n2; q += blockDim.x) {
+    const int r = q / n2, e = q - r * n2;
+    cs[r][e] = (j0 + r < nf) ? c[((long long)(j0 + r) * g.nblk + A) * n2 + e] : mk<T>(0, 0);
+  }
   __syncthreads();
   if (t >= g.bvol) return;
   const int s = A * g.bvol + t;
-  cplx<T> out[12];
+  cplx<T> out[R][12];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) out[i] = mk<T>(0, 0);
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) out[r][i] = mk<T>(0, 0);
   for (int k = 0; k < Nv; ++k) {
     const cplx<T> *Pk = P + (long long)k * 12 * g.V;
-    const cplx<T> c0 = cs[k], c1 = cs[Nv + k];
+    cplx<T> pv[12];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) out[i] = out[i] + Pk[(long long)i * g.V + s] * (i < 6 ? c0 : c1);
+    for (int i = 0; i < 12; ++i) pv[i] = Pk[(long long)i * g.V + s];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const cplx<T> c0 = cs[r][k], c1 = cs[r][Nv + k];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) out[r][i] = out[r][i] + pv[i] * (i < 6 ? c0 : c1);
+    }
   }
-  cplx<T> *fj = f + j * fstride;
 #pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    const long long e = (long long)i * g.V + s;
-    fj[e] = acc ? fj[e] + out[i] : out[i];
+  for (int r = 0; r < R; ++r) {
+    if (j0 + r >= nf) break;
+    cplx<T> *fj = f + (j0 + r) * fstride;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const long long e = (long long)i * g.V + s;
+      fj[e] = acc ? fj[e] + out[r][i] : out[r][i];
+    }
   }
 }
+
+// fields per workgroup of the transfer kernels: 4 in FP32, 2 in FP64 (registers)
+template <typename T> constexpr int transfer_group() { return sizeof(T) == 4 ? 4 : 2; }
 
 // Cholesky-QR, applied twice, of the (6*bvol) x Nv local matrix of aggregate
 // A and gamma5 half h.  Gram G = W^dag W, G = L L^dag, P = W L^-dag; the QR
@@ -190,7 +221,9 @@ template <typename T>
 void launch_restrict(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *f, long long fstride, int nf,
                      cplx<T> *c, hipStream_t st) {
   const int threads = ((g.bvol + 63) / 64) * 64;
-  hipLaunchKernelGGL((k_restrict<T>), dim3(g.nblk, nf), dim3(threads), 0, st, g, P, Nv, f, fstride, c);
+  constexpr int R = transfer_group<T>();
+  hipLaunchKernelGGL((k_restrict<T, R>), dim3(g.nblk, (nf + R - 1) / R), dim3(threads), 0, st, g, P, Nv, f, fstride,
+                     nf, c);
   LQ_HIP(hipGetLastError());
 }
 
@@ -198,8 +231,9 @@ template <typename T>
 void launch_prolong(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *c, cplx<T> *f, long long fstride,
                     int nf, bool accumulate, hipStream_t st) {
   const int threads = ((g.bvol + 63) / 64) * 64;
-  hipLaunchKernelGGL((k_prolong<T>), dim3(g.nblk, nf), dim3(threads), 0, st, g, P, Nv, c, f, fstride,
-                     accumulate);
+  constexpr int R = transfer_group<T>();
+  hipLaunchKernelGGL((k_prolong<T, R>), dim3(g.nblk, (nf + R - 1) / R), dim3(threads), 0, st, g, P, Nv, c, f,
+                     fstride, nf, accumulate);
   LQ_HIP(hipGetLastError());
 }
 

@@ -76,6 +76,52 @@ def test_q_apply_many_rhs_chunks():
     assert relmax(y, ref) < 1e-13
 
 
+def test_q_apply_full_size_sampled_sites():
+    # 32^3 x 64, the benchmark lattice: sampled output sites against the
+    # oracle's site-by-site evaluation of the definition.
+    from oracle.dirac import apply_Q_sites
+    dims = (32, 32, 32, 64)
+    U = lqsynth.gauge_field(dims, 0.25, 301)
+    lat = Lattice(dims, 1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    V = lat.V
+    x = torch.complex(torch.randn((1, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((1, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    c = _ctx(dims, 1)
+    Ud = dev(U)
+    y64 = c.q_apply(Ud, -0.156781, x)
+    y32 = c.q_apply(Ud.to(torch.complex64), -0.156781, x.to(torch.complex64))
+    rng = np.random.default_rng(8)
+    sites = np.concatenate([[0, V - 1, 31, 32 * 32 * 32 * 63], rng.integers(0, V, 60)])
+    xs = host(x[0])
+    ref = apply_Q_sites(U, -0.156781, xs, lat, sites)
+    assert relmax(host(y64[0])[:, sites], ref) < 1e-13
+    assert relmax(host(y32[0])[:, sites], ref) < 2e-6
+
+
+def test_coarse_apply_many_sites():
+    # 8192 coarse sites: the all-rhs-per-workgroup coarse kernel
+    dims, agg = (16, 16, 16, 32), (2, 2, 2, 2)
+    U = lqsynth.gauge_field(dims, 0.25, 31)
+    lat = Lattice(dims, 1)
+    from paper_1509_06865_amd import MGParams
+    c = _ctx(dims, 1)
+    c.mg_setup(dev(U), -0.15, agg, dev(lqsynth.gaussian_spinors(4, dims, 32)),
+               MGParams(precision=0, n_setup=0, n_init=1))
+    P = host(c.get_interp())
+    ag = M.Aggregation(lat, agg)
+    Qc = M.coarse_operator(WilsonOp(U, -0.15, lat), ag, P)
+    assert relmax(host(c.get_coarse()), Qc[:, :5]) < 1e-12
+    rng = np.random.default_rng(33)
+    nr = 11
+    x = rng.standard_normal((nr, ag.nA, 8)) + 1j * rng.standard_normal((nr, ag.nA, 8))
+    sig = [0.02 * k for k in range(nr)]
+    y = host(c.coarse_apply(sig, dev(x)))
+    ref = np.stack([M.coarse_apply(Qc, ag, x[k], sig[k]) for k in range(nr)])
+    assert relmax(y, ref) < 1e-12
+
+
 @pytest.mark.parametrize("nb,nw,n", [(1, 1, 7), (17, 5, 1000), (100, 16, 4096 * 3 + 29), (192, 16, 300)])
 def test_inner_products_match_numpy(nb, nw, n):
     rng = np.random.default_rng(nb * 31 + nw)
@@ -133,11 +179,14 @@ def test_restrict_prolong_match(hier):
 def test_coarse_apply_matches(hier):
     Qc = M.coarse_operator(hier["op"], hier["ag"], hier["P"])
     rng = np.random.default_rng(12)
-    x = rng.standard_normal((2, hier["ag"].nA, 16)) + 1j * rng.standard_normal((2, hier["ag"].nA, 16))
-    sig = [0.0, 0.031]
-    y = host(hier["c"].coarse_apply(sig, dev(x)))
-    ref = np.stack([M.coarse_apply(Qc, hier["ag"], x[k], sig[k]) for k in range(2)])
-    assert relmax(y, ref) < _tol(hier) * 3
+    # one wave per (site, rhs) on this small coarse grid (the all-rhs form is
+    # used from 1024 coarse sites on and is covered by the sampled large test)
+    for nr in (2, 11):
+        x = rng.standard_normal((nr, hier["ag"].nA, 16)) + 1j * rng.standard_normal((nr, hier["ag"].nA, 16))
+        sig = [0.031 * k for k in range(nr)]
+        y = host(hier["c"].coarse_apply(sig, dev(x)))
+        ref = np.stack([M.coarse_apply(Qc, hier["ag"], x[k], sig[k]) for k in range(nr)])
+        assert relmax(y, ref) < _tol(hier) * 3
 
 
 def test_sap_smoother_matches(hier):
