@@ -83,6 +83,11 @@ typedef struct {
   int rqi_deflate;      /* RQI: 1 = before each multigrid cycle, solve Q - sigma
                            exactly on the span of the current eigenvector
                            approximations (Galerkin correction, FP64) */
+  int rqi_start_passes; /* RQI: passes of the setup's multigrid iteration (sec. 2.1)
+                           over all start vectors before Alg. 1: v <- M_0 v with
+                           the sigma = 0 preconditioner, re-orthonormalisation and
+                           a Rayleigh-Ritz step; 0 = Alg. 1 from the start vectors
+                           as given */
 } lq_mg_params;
 
 typedef struct {

@@ -55,6 +55,7 @@ class MGParams:
     fgmres_restarts: int = 40
     n_init: int = 2              # setup: initial smoother passes
     n_setup: int = 4             # setup: multigrid passes
+    coarse_direct: bool = False  # exact dense coarse solve (the two-grid method of eq. E_2g)
 
 
 class Aggregation:
@@ -309,10 +310,12 @@ class TwoLevel:
         self.params = params or MGParams()
         self.P = None
         self.Qc = None
+        self._Qc_dense = None
 
     def set_vectors(self, W):
         self.P = build_P(W, self.ag)
         self.Qc = coarse_operator(self.op, self.ag, self.P)
+        self._Qc_dense = None
 
     def A(self, sigma, x):
         return self.op.Q(x) - sigma * x
@@ -333,8 +336,15 @@ class TwoLevel:
         same solution, but the operator's field of values lies near the right
         half plane instead of straddling zero.  Stops when the residual of the
         equivalent system (equal in norm to that of the original one) is
-        <= coarse_tol * ||c||, or after coarse_restarts + 1 cycles."""
+        <= coarse_tol * ||c||, or after coarse_restarts + 1 cycles.  With
+        ``coarse_direct`` the coarse system is solved exactly instead."""
         p = self.params
+        if p.coarse_direct:
+            # exact coarse-grid correction (Q_c - sigma)^{-1} c, dense LU
+            if self._Qc_dense is None:
+                self._Qc_dense = dense_coarse(self.Qc, self.ag)
+            M = self._Qc_dense - sigma * np.eye(self._Qc_dense.shape[0])
+            return np.linalg.solve(M, c.reshape(-1)).reshape(c.shape)
         g5c = coarse_gamma5(self.P.shape[0])
 
         def op(v):

@@ -71,18 +71,25 @@ __device__ inline void link_mul(const cplx<T> m[9], const Half2<T> &h, Half2<T> 
     }
 }
 
+// acc += sign * (1 - gamma_mu) m p        (fwd = true)
+// acc += sign * (1 + gamma_mu) m^dag p    (fwd = false), m a loaded link
+template <typename T>
+__device__ inline void hop_link(int mu, bool fwd, const cplx<T> p[12], const cplx<T> m[9], T sign, cplx<T> acc[12]) {
+  const T e = fwd ? (T)-1 : (T)1;
+  Half2<T> h, u;
+  project(mu, e, p, h);
+  link_mul(m, h, u, !fwd);
+  reconstruct(mu, e, u, sign, acc);
+}
+
 // acc += sign * (1 - gamma_mu) U_mu(link_site) p        (fwd = true)
 // acc += sign * (1 + gamma_mu) U_mu(link_site)^dag p    (fwd = false)
 template <typename T>
 __device__ inline void hop(int mu, bool fwd, const cplx<T> p[12], const cplx<T> *__restrict__ U, long long V,
                            int link_site, T sign, cplx<T> acc[12]) {
-  const T e = fwd ? (T)-1 : (T)1;
-  Half2<T> h, u;
-  project(mu, e, p, h);
   cplx<T> m[9];
   load_link(U, V, mu, link_site, m);
-  link_mul(m, h, u, !fwd);
-  reconstruct(mu, e, u, sign, acc);
+  hop_link(mu, fwd, p, m, sign, acc);
 }
 
 }  // namespace lq

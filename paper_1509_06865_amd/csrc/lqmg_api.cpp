@@ -885,6 +885,7 @@ int lq_params_default(lq_mg_params *p) {
   p->rqi_guard = 2;
   p->rqi_solve_restarts = 1;
   p->rqi_deflate = 1;
+  p->rqi_start_passes = 0;
   return LQ_OK;
 }
 
@@ -975,6 +976,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
     if (p.precision != LQ_PREC_FP64 && p.precision != LQ_PREC_MIXED) fail(LQ_ERR_ARG, "bad precision");
     if (p.rqi_block < 1 || p.rqi_block > kMaxRhs) fail(LQ_ERR_ARG, "rqi_block must be in 1..16");
     if (p.rqi_guard < 0) fail(LQ_ERR_ARG, "rqi_guard must be >= 0");
+    if (p.rqi_start_passes < 0) fail(LQ_ERR_ARG, "rqi_start_passes must be >= 0");
     if (p.coarse_m < 1 || p.fgmres_m < 1 || p.sap_mr < 0 || p.post < 0 || p.pre < 0)
       fail(LQ_ERR_ARG, "bad iteration parameters");
     c->have = false;
@@ -1149,6 +1151,53 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         }
       }
     };
+    // Rayleigh-Ritz on E[L..nw) (orthonormal, orthogonal to E[0..L)), then
+    // lambda and eps of those vectors.  The FGMRES basis vectors (V, then Z)
+    // are idle here and hold the rotated vectors; only if they are too few is
+    // more memory taken.
+    auto rr_tail = [&](int L) {
+      std::vector<c128 *> spill;
+      const size_t nV = c->fine_kw.V.n / V12, nZ = c->fine_kw.Z.n / V12;
+      if (nV + nZ >= (size_t)(nw - L)) {
+        for (int j = 0; j < nw - L; ++j)
+          spill.push_back((size_t)j < nV ? c->fine_kw.V.p + j * V12 : c->fine_kw.Z.p + (j - nV) * V12);
+      } else {
+        c128 *sp = c->fine_kw.V.get((size_t)(nw - L) * V12);
+        for (int j = 0; j < nw - L; ++j) spill.push_back(sp + j * V12);
+      }
+      rayleigh_ritz_tail(c, E, nw, L, lam, spill);
+      std::vector<int> U;
+      for (int i = L; i < nw; ++i) U.push_back(i);
+      rq_resid(U);
+    };
+    // Start passes: the setup's multigrid iteration (sec. 2.1) over every
+    // start vector, v <- M_0 v with the sigma = 0 preconditioner, keeping the
+    // set orthonormal; a Rayleigh-Ritz step then gives lambda_i and eps_i, and
+    // P is rebuilt from the vectors with the smallest |lambda|.
+    for (int pass = 0; pass < c->p.rqi_start_passes; ++pass) {
+      double t0 = now();
+      std::vector<double> zs(kMaxRhs, 0.0);
+      for (int k0 = 0; k0 < nw; k0 += kMaxRhs) {
+        const int nk = std::min(kMaxRhs, nw - k0);
+        precond64(c, zs.data(), E + k0 * V12, X, nk);
+        copy<double>(c, E + k0 * V12, X, (size_t)nk * V12);
+      }
+      S.t_solve += now() - t0;
+      t0 = now();
+      orthonormalise(c, E, nw);
+      S.t_ortho += now() - t0;
+      t0 = now();
+      if (c->p.rayleigh_ritz) rr_tail(0);
+      else rq_resid([&] { std::vector<int> a(nw); for (int i = 0; i < nw; ++i) a[i] = i; return a; }());
+      S.t_rq += now() - t0;
+      rebuild_from({0.0});
+      if (verbose()) {
+        double emax = 0;
+        for (int i = 0; i < nw; ++i) emax = std::max(emax, eps[i]);
+        std::fprintf(stderr, "[lqmg] rqi start pass %d/%d: max eps %.3e\n", pass + 1, c->p.rqi_start_passes, emax);
+        std::fflush(stderr);
+      }
+    }
     bool done = false;
     while (!done && S.sweeps < c->p.rqi_max_sweeps) {
       std::vector<int> todo;
@@ -1240,21 +1289,7 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
           for (int p = 0; p < nw; ++p) { l2[p] = lam[order[p]]; e2[p] = eps[order[p]]; }
           lam = l2;
           eps = e2;
-          // the FGMRES basis vectors (V, then Z) are idle here and hold the
-          // rotated vectors; only if they are too few is more memory taken
-          std::vector<c128 *> spill;
-          const size_t nV = c->fine_kw.V.n / V12, nZ = c->fine_kw.Z.n / V12;
-          if (nV + nZ >= (size_t)(nw - L)) {
-            for (int j = 0; j < nw - L; ++j)
-              spill.push_back((size_t)j < nV ? c->fine_kw.V.p + j * V12 : c->fine_kw.Z.p + (j - nV) * V12);
-          } else {
-            c128 *sp = c->fine_kw.V.get((size_t)(nw - L) * V12);
-            for (int j = 0; j < nw - L; ++j) spill.push_back(sp + j * V12);
-          }
-          rayleigh_ritz_tail(c, E, nw, L, lam, spill);
-          std::vector<int> U;
-          for (int i = L; i < nw; ++i) U.push_back(i);
-          rq_resid(U);
+          rr_tail(L);
           S.t_rq += now() - t0;
           if (nw <= Nv) rebuild_from({0.0});
         }

@@ -17,17 +17,49 @@ __device__ inline double wsum(double v) {
   return v;
 }
 
+// Wave sum of N values per lane (N a power of two, at most 64) by a transposed
+// butterfly: at offset o each lane keeps half of its values, hands the other
+// half to lane ^ o and adds what it receives, so N values cost N - 1 shuffles
+// before the last log2(64 / N) plain steps.  Afterwards every lane holds the
+// complete sum of value (lane / (64 / N)).
+template <typename T, int N, int C, int O>
+__device__ inline void transpose_step(T (&v)[N], int lane) {
+  if constexpr (C > 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int j = 0; j < C / 2; ++j) {
+      const T give = up ? v[j] : v[j + C / 2];
+      const T keep = up ? v[j + C / 2] : v[j];
+      v[j] = keep + __shfl_xor(give, O, 64);
+    }
+    transpose_step<T, N, C / 2, O / 2>(v, lane);
+  }
+}
+
+template <typename T, int N>
+__device__ inline T transpose_reduce(T (&v)[N], int lane) {
+  transpose_step<T, N, N, 32>(v, lane);
+  T x = v[0];
+#pragma unroll
+  for (int o = 32 / N; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
 // c[j][A][h*Nv + k] = sum over the aggregate's sites of conj(P_k) . f_j on half h.
 // One workgroup per (aggregate, group of R fields): each P_k value is loaded
-// once for the R fields held in registers.
+// once for the R fields held in registers.  Per k a lane forms 4R partial sums
+// (field, half, re/im); a transposed butterfly reduces them over the wave and
+// the waves' results meet in LDS.
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_restrict(Geom g, const cplx<T> *__restrict__ P, int Nv,
                                                   const cplx<T> *__restrict__ f, long long fstride, int nf,
                                                   cplx<T> *__restrict__ c) {
-  __shared__ double part[4][32][R][4];     // [wave][k][field][h re, h im]
+  constexpr int NV = 4 * R;
+  __shared__ T part[4][32][NV];          // [wave][k][field * 4 + half * 2 + re/im]
   const int A = blockIdx.x, j0 = blockIdx.y * R;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
   const bool active = t < g.bvol;
+  // idle lanes read a valid site and hold zero fields, so their products vanish
   const int s = A * g.bvol + (active ? t : 0);
   cplx<T> fv[R][12];
 #pragma unroll
@@ -39,22 +71,21 @@ __global__ void __launch_bounds__(256) k_restrict(Geom g, const cplx<T> *__restr
     cplx<T> pv[12];
     const cplx<T> *Pk = P + (long long)k * 12 * g.V;
 #pragma unroll
-    for (int i = 0; i < 12; ++i) pv[i] = active ? Pk[(long long)i * g.V + s] : mk<T>(0, 0);
+    for (int i = 0; i < 12; ++i) pv[i] = Pk[(long long)i * g.V + s];
+    T v[NV];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+      T a0r = 0, a0i = 0, a1r = 0, a1i = 0;
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
-        const double re = (double)pv[i].re * fv[r][i].re + (double)pv[i].im * fv[r][i].im;
-        const double im = (double)pv[i].re * fv[r][i].im - (double)pv[i].im * fv[r][i].re;
+        const T re = pv[i].re * fv[r][i].re + pv[i].im * fv[r][i].im;
+        const T im = pv[i].re * fv[r][i].im - pv[i].im * fv[r][i].re;
         if (i < 6) { a0r += re; a0i += im; } else { a1r += re; a1i += im; }
       }
-      a0r = wsum(a0r); a0i = wsum(a0i); a1r = wsum(a1r); a1i = wsum(a1i);
-      if (lane == 0) {
-        part[wave][k][r][0] = a0r; part[wave][k][r][1] = a0i;
-        part[wave][k][r][2] = a1r; part[wave][k][r][3] = a1i;
-      }
+      v[4 * r + 0] = a0r; v[4 * r + 1] = a0i; v[4 * r + 2] = a1r; v[4 * r + 3] = a1i;
     }
+    const T sum = transpose_reduce<T, NV>(v, lane);
+    if ((lane & (64 / NV - 1)) == 0) part[wave][k][lane / (64 / NV)] = sum;
   }
   __syncthreads();
   const int n2 = 2 * Nv;
@@ -62,9 +93,9 @@ __global__ void __launch_bounds__(256) k_restrict(Geom g, const cplx<T> *__restr
     const int r = q / n2, e = q - r * n2;
     if (j0 + r >= nf) continue;
     const int h = e / Nv, k = e - h * Nv;
-    double re = 0, im = 0;
-    for (int w = 0; w < nw; ++w) { re += part[w][k][r][2 * h]; im += part[w][k][r][2 * h + 1]; }
-    c[((long long)(j0 + r) * g.nblk + A) * n2 + e] = mk<T>((T)re, (T)im);
+    T re = 0, im = 0;
+    for (int w = 0; w < nw; ++w) { re += part[w][k][4 * r + 2 * h]; im += part[w][k][4 * r + 2 * h + 1]; }
+    c[((long long)(j0 + r) * g.nblk + A) * n2 + e] = mk<T>(re, im);
   }
 }
 

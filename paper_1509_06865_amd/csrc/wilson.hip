@@ -8,41 +8,61 @@
 namespace lq {
 namespace {
 
-template <typename T, int MODE>
+// One thread per site and R right-hand sides: each link is loaded once and
+// applied to the R fields, so the links are read once per group of R fields.
+template <typename T, int MODE, int R>
 __global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restrict__ U,
                                                 const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
-                                                const cplx<T> *__restrict__ bin, T m0, Shifts sig) {
+                                                const cplx<T> *__restrict__ bin, T m0, Shifts sig, int nrhs) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
-  const int k = blockIdx.y;
-  const long long off = (long long)k * 12 * g.V;
-  const cplx<T> *x = xin + off;
+  const int k0 = blockIdx.y * R;
+  const int nr = (nrhs - k0 < R) ? nrhs - k0 : R;      // same for the whole launch row
+  const long long fs = 12LL * g.V;
+  const cplx<T> *x = xin + k0 * fs;
   const SiteCoord c = decode(g, s);
-  cplx<T> acc[12], p[12];
+  cplx<T> acc[R][12], p[12], m[9];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[r][i] = mk<T>(0, 0);
   // a rolled loop over directions bounds the live ranges (one hop pair at a time)
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     float sg;
     bool in;
     const int sf = neighbour(g, s, c, mu, true, &sg, &in);
-    load_spinor(x, g.V, sf, p);
-    hop(mu, true, p, U, g.V, s, (T)sg, acc);
-    const int sb = neighbour(g, s, c, mu, false, &sg, &in);
-    load_spinor(x, g.V, sb, p);
-    hop(mu, false, p, U, g.V, sb, (T)sg, acc);
-  }
-  load_spinor(x, g.V, s, p);
-  const T diag = (T)4 + m0;
-  const T sgm = (T)sig.s[k];
+    load_link(U, g.V, mu, s, m);
 #pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    cplx<T> d = diag * p[i] - (T)0.5 * acc[i];
-    if (i >= 6) d = -d;                        // gamma5
-    d = d - sgm * p[i];
-    if (MODE == W_RESID) d = bin[off + (long long)i * g.V + s] - d;
-    yout[off + (long long)i * g.V + s] = d;
+    for (int r = 0; r < R; ++r) {
+      if (r >= nr) break;
+      load_spinor(x + r * fs, g.V, sf, p);
+      hop_link(mu, true, p, m, (T)sg, acc[r]);
+    }
+    const int sb = neighbour(g, s, c, mu, false, &sg, &in);
+    load_link(U, g.V, mu, sb, m);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r >= nr) break;
+      load_spinor(x + r * fs, g.V, sb, p);
+      hop_link(mu, false, p, m, (T)sg, acc[r]);
+    }
+  }
+  const T diag = (T)4 + m0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r >= nr) break;
+    const long long off = (k0 + r) * fs;
+    load_spinor(x + r * fs, g.V, s, p);
+    const T sgm = (T)sig.s[k0 + r];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      cplx<T> d = diag * p[i] - (T)0.5 * acc[r][i];
+      if (i >= 6) d = -d;                        // gamma5
+      d = d - sgm * p[i];
+      if (MODE == W_RESID) d = bin[off + (long long)i * g.V + s] - d;
+      yout[off + (long long)i * g.V + s] = d;
+    }
   }
 }
 
@@ -103,14 +123,27 @@ __global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__r
 
 }  // namespace
 
+// fields per thread in the Wilson kernel: registers allow 2 in FP64, 4 in FP32
+template <typename T> constexpr int wilson_group() { return sizeof(T) == 4 ? 4 : 2; }
+
 template <typename T>
 void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y, const cplx<T> *b,
                    double m0, const Shifts &sig, int nrhs, int mode, hipStream_t st) {
-  dim3 grid(blocks_for(g.V, 256), nrhs);
-  if (mode == W_QSHIFT)
-    hipLaunchKernelGGL((k_wilson<T, W_QSHIFT>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig);
-  else
-    hipLaunchKernelGGL((k_wilson<T, W_RESID>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig);
+  if (nrhs <= 0) return;
+  constexpr int R = wilson_group<T>();
+  if (nrhs == 1) {
+    const dim3 grid(blocks_for(g.V, 256), 1);
+    if (mode == W_QSHIFT)
+      hipLaunchKernelGGL((k_wilson<T, W_QSHIFT, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+    else
+      hipLaunchKernelGGL((k_wilson<T, W_RESID, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+  } else {
+    const dim3 grid(blocks_for(g.V, 256), (nrhs + R - 1) / R);
+    if (mode == W_QSHIFT)
+      hipLaunchKernelGGL((k_wilson<T, W_QSHIFT, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+    else
+      hipLaunchKernelGGL((k_wilson<T, W_RESID, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+  }
   LQ_HIP(hipGetLastError());
 }
 

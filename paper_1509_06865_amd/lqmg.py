@@ -38,7 +38,7 @@ class _Params(C.Structure):
                 ("fgmres_restarts", C.c_int), ("n_init", C.c_int), ("n_setup", C.c_int),
                 ("rqi_block", C.c_int), ("rqi_max_sweeps", C.c_int), ("rqi_solve_tol", C.c_double),
                 ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int), ("rqi_solve_restarts", C.c_int),
-                ("rqi_deflate", C.c_int)]
+                ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int)]
 
 
 class _SolveStats(C.Structure):
@@ -74,6 +74,7 @@ class MGParams:
     rqi_guard: int | None = None
     rqi_solve_restarts: int | None = None
     rqi_deflate: int | None = None
+    rqi_start_passes: int | None = None
 
     def to_c(self, lib) -> _Params:
         p = _Params()
