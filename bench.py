@@ -80,9 +80,11 @@ def time_q_apply(ctx, U, m0, x, reps, torch):
     return start.elapsed_time(stop) / reps / 1e3
 
 
-def cpu_baseline(U_host, m0, dims, t_bc, x_host):
-    """The oracle's FP64 Q apply (definition route) on the full lattice, timed
-    on the host: the CPU reference for the Dirac-apply part of the metric."""
+def cpu_baseline(U_host, m0, dims, t_bc, x_host, n_outer):
+    """The oracle's FP64 Q apply (definition route) timed on the host on the
+    full lattice, scaled by the step's outer FGMRES iterations (each applies Q
+    once): a lower bound on the oracle's time for the same eigensolve, which
+    also needs the smoother, the coarse solves and the orthogonalisation."""
     from oracle.dirac import Lattice, apply_Q
     lat = Lattice(dims, t_bc)
     lat.tables()                                   # neighbour tables built outside the timing
@@ -93,11 +95,33 @@ def cpu_baseline(U_host, m0, dims, t_bc, x_host):
         if time.perf_counter() - t0 > 10.0 or reps >= 3:
             break
     t = (time.perf_counter() - t0) / reps
+    return {"value": round(t * n_outer, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} FP64 Q applies of the oracle's numpy definition on the full {dims} lattice, "
+                      f"{t:.2f} s each, times the {n_outer} outer FGMRES iterations of the GPU step (one Q "
+                      f"apply each): a lower bound for the oracle's eigensolve, whose smoother, coarse solves "
+                      f"and orthogonalisation are not counted"}
+
+
+def kernel_only(args):
+    """Launch only the roofline kernel (FP64 q_apply on the workload's lattice)
+    and a plain device copy of known size, for hardware-counter passes."""
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import Context
+    gold = load_golden(WORKLOADS[args.workload]["golden"])
+    dims, t_bc = tuple(gold["dims"]), gold["t_bc"]
     V = int(np.prod(dims))
-    return {"value": round(960.0 * V / t / 1e9, 3), "unit": "GB/s (Dirac apply, FP64, algorithmic bytes)",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{reps} FP64 Q applies of the oracle's numpy definition on the full {dims} lattice "
-                      f"({t:.2f} s each); the eigensolve itself is not run on the CPU"}
+    U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
+    x = device_gaussian(1, dims, gold["field_seed"] + 3, torch)
+    ctx = Context(dims, t_bc)
+    t = time_q_apply(ctx, U, gold["m0"], x, 10, torch)
+    a = torch.empty(12 * V * 2, dtype=torch.float64, device="cuda").normal_()
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"kernel-only: q_apply FP64 {t * 1e3:.3f} ms ({960.0 * V / t / 1e9:.0f} GB/s algorithmic); "
+        f"copy of {a.numel() * 8} bytes x10")
 
 
 def main():
@@ -112,11 +136,16 @@ def main():
     ap.add_argument("--nv", type=int, default=None)
     ap.add_argument("--max-sweeps", type=int, default=40)
     ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="run only the roofline kernel and a reference copy (for counter passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
               f"described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
+    if args.kernel_only:
+        kernel_only(args)
+        return
 
     import torch
     import lqsynth
@@ -201,7 +230,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle Q apply on the host)")
         x_host = x[0].cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(U_host, m0, dims, t_bc, x_host)
+        out["cpu_baseline"] = cpu_baseline(U_host, m0, dims, t_bc, x_host, info["fgmres_iters"])
     print(json.dumps(out), flush=True)
 
 

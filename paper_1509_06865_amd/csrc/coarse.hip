@@ -51,17 +51,22 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T
 
 // All right-hand sides of one coarse site per workgroup: each (2Nv)^2 block is
 // staged in LDS once and applied to every rhs, so the operator is read once
-// per call instead of once per rhs.  Thread t owns rows t % n2 .. for the rhs
-// t / n2, t / n2 + 256 / n2, ...
+// per call instead of once per rhs.  Thread t owns row t % n2 for the rhs
+// t / n2, t / n2 + 256 / n2, ...  The LDS rows are padded by one element, so
+// threads reading the same column of different rows hit different banks, and
+// the next block is loaded into registers while the current one is applied.
+constexpr int kCoarseMaxN2 = 64;
+constexpr int kCoarsePerThread = (kCoarseMaxN2 * kCoarseMaxN2 + 255) / 256;
+
 template <typename T, int KCH>
 __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
                                                             const cplx<T> *__restrict__ xin,
                                                             cplx<T> *__restrict__ yout, Shifts sig, bool g5form,
                                                             int nrhs) {
-  __shared__ cplx<T> blk[64 * 64];
-  __shared__ cplx<T> xs[KCH][64];
+  __shared__ cplx<T> blk[kCoarseMaxN2 * (kCoarseMaxN2 + 1)];
+  __shared__ cplx<T> xs[KCH][kCoarseMaxN2];
   const int A = blockIdx.x;
-  const int n2 = cg.n2;
+  const int n2 = cg.n2, ld = n2 + 1;
   const long long bs = (long long)n2 * n2;
   int nb[9];
   nb[0] = A;
@@ -70,29 +75,55 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
   const int rows_per = n2;                          // threads per rhs
   const int rhs_slots = 256 / rows_per;             // rhs handled at once
   const int i = t % rows_per, ks = t / rows_per;
+  auto block_ptr = [&](int d) {
+    return (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
+  };
   for (int k0 = 0; k0 < nrhs; k0 += KCH) {
     const int kc = (nrhs - k0 < KCH) ? nrhs - k0 : KCH;
     cplx<T> acc[(KCH + 3) / 4 > 0 ? (KCH + 3) / 4 : 1];
     const int nacc = (kc + rhs_slots - 1) / rhs_slots;
     for (int a = 0; a < (int)(sizeof(acc) / sizeof(acc[0])); ++a) acc[a] = mk<T>(0, 0);
+    cplx<T> pre[kCoarsePerThread];
+    {
+      const cplx<T> *M = block_ptr(0);
+#pragma unroll
+      for (int q = 0; q < kCoarsePerThread; ++q) {
+        const int e = t + 256 * q;
+        pre[q] = (e < n2 * n2) ? M[e] : mk<T>(0, 0);
+      }
+    }
     for (int d = 0; d < 9; ++d) {
       __syncthreads();
-      const cplx<T> *M = (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
-      for (int e = t; e < n2 * n2; e += 256) blk[e] = M[e];
+#pragma unroll
+      for (int q = 0; q < kCoarsePerThread; ++q) {
+        const int e = t + 256 * q;
+        if (e < n2 * n2) {
+          const int r = e / n2, c = e - r * n2;
+          blk[r * ld + c] = pre[q];
+        }
+      }
       for (int e = t; e < kc * n2; e += 256) {
         const int k = e / n2, j = e - k * n2;
         xs[k][j] = xin[((long long)(k0 + k) * cg.nA + nb[d]) * n2 + j];
       }
       __syncthreads();
+      if (d + 1 < 9) {
+        const cplx<T> *M = block_ptr(d + 1);
+#pragma unroll
+        for (int q = 0; q < kCoarsePerThread; ++q) {
+          const int e = t + 256 * q;
+          pre[q] = (e < n2 * n2) ? M[e] : mk<T>(0, 0);
+        }
+      }
       if (i < n2)
         for (int a = 0; a < nacc; ++a) {
           const int k = ks + a * rhs_slots;
           if (k >= kc) break;
           cplx<T> s = mk<T>(0, 0);
           if (d < 5)
-            for (int j = 0; j < n2; ++j) s = s + blk[i * n2 + j] * xs[k][j];
+            for (int j = 0; j < n2; ++j) s = s + blk[i * ld + j] * xs[k][j];
           else
-            for (int j = 0; j < n2; ++j) s = s + cmul_conj(blk[j * n2 + i], xs[k][j]);
+            for (int j = 0; j < n2; ++j) s = s + cmul_conj(blk[j * ld + i], xs[k][j]);
           acc[a] = acc[a] + s;
         }
     }

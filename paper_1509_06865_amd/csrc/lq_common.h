@@ -114,6 +114,17 @@ struct HipError {
 
 inline unsigned blocks_for(long long n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+// The dispatcher hands consecutive workgroups of a launch to the 8 XCDs in
+// turn, and each XCD has its own L2.  Renumbering the workgroups so that XCD x
+// runs one contiguous range of tiles keeps stencil neighbours in one L2.  A
+// bijection of [0, n) for any n.
+constexpr int kNumXcd = 8;
+__device__ inline int xcd_tile(int b, int n) {
+  const int q = n / kNumXcd, r = n % kNumXcd;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Per-rhs scalar passed to kernels: shifts, coefficients.
 constexpr int kMaxRhs = 16;
 

@@ -803,6 +803,28 @@ void projected_operator(lq_ctx *c, const c128 *E, int n, std::vector<cd> &A, std
   }
 }
 
+// After the fields E[ids[q]] were replaced by X[q] (q < nk, already copied into
+// E), update their columns of A = E^dag Q E and G = E^dag E, and their rows by
+// Hermiticity; the other entries do not change.
+void update_projected(lq_ctx *c, const c128 *E, int n, const std::vector<int> &ids, const c128 *X,
+                      std::vector<cd> &A, std::vector<cd> &G) {
+  const long long V12 = 12LL * c->g.V;
+  const int nk = (int)ids.size();
+  c128 *QX = c->defl_tmp.get((size_t)kMaxRhs * V12);
+  launch_wilson<double>(c->g, c->U64.p, X, QX, nullptr, c->m0, shifts_of(nullptr, 0), nk, W_QSHIFT, c->st);
+  auto a = gram(c, n, E, V12, nk, QX, V12, V12);
+  auto g = gram(c, n, E, V12, nk, X, V12, V12);
+  for (int q = 0; q < nk; ++q) {
+    const int i = ids[q];
+    for (int j = 0; j < n; ++j) {
+      A[(size_t)j * n + i] = a[(size_t)j * nk + q];
+      A[(size_t)i * n + j] = std::conj(a[(size_t)j * nk + q]);
+      G[(size_t)j * n + i] = g[(size_t)j * nk + q];
+      G[(size_t)i * n + j] = std::conj(g[(size_t)j * nk + q]);
+    }
+  }
+}
+
 // out = u + B_sigma(in - (Q - sigma) u) with u the Galerkin correction on span(E).
 void deflated_precond(lq_ctx *c, const Deflation &D, const double *sig, const c128 *in, c128 *out, int nrhs) {
   const long long n = 12LL * c->g.V;
@@ -1135,6 +1157,13 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     c128 *X = c->tmpB.get((size_t)kMaxRhs * V12);
     c128 *B = c->tmpA.get((size_t)kMaxRhs * V12);
     const int nb = c->p.rqi_block;
+    // the FGMRES basis takes its solve shape now: Rayleigh-Ritz borrows it as
+    // scratch, and sizing it for that first would leave no room for the solves
+    {
+      const size_t blk = (size_t)std::min(nb, nw);
+      c->fine_kw.V.get((size_t)(c->p.fgmres_m + 1) * blk * V12);
+      c->fine_kw.Z.get((size_t)c->p.fgmres_m * blk * V12);
+    }
     // lambda_i and eps_i = ||Q v_i - lambda_i v_i|| for the listed vectors
     auto rq_resid = [&](const std::vector<int> &ids) {
       for (size_t q0 = 0; q0 < ids.size(); q0 += kMaxRhs) {
@@ -1198,6 +1227,10 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         std::fflush(stderr);
       }
     }
+    // A = E^dag Q E and G = E^dag E for the Galerkin correction, kept up to date
+    // column by column as block members change; recomputed after rotations
+    std::vector<cd> Aop, Gop;
+    bool ag_valid = false;
     bool done = false;
     while (!done && S.sweeps < c->p.rqi_max_sweeps) {
       std::vector<int> todo;
@@ -1216,11 +1249,13 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         double t0 = now();
         Deflation D;
         if (c->p.rqi_deflate) {
-          std::vector<cd> A, G;
-          projected_operator(c, E, nw, A, G);
+          if (!ag_valid) {
+            projected_operator(c, E, nw, Aop, Gop);
+            ag_valid = true;
+          }
           D.E = E;
           D.n = nw;
-          deflation_factor(D, A, G, sig.data(), nk);
+          deflation_factor(D, Aop, Gop, sig.data(), nk);
         }
         int its[kMaxRhs];
         double rr[kMaxRhs];
@@ -1258,6 +1293,8 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
           scale<double>(c, std::vector<cd>{cd(1.0 / nr[0])}, x, 0, x, 0, V12, 1, false);
           copy<double>(c, E + i * V12, x, V12);
         }
+        if (c->p.rqi_deflate && ag_valid)
+          update_projected(c, E, nw, std::vector<int>(todo.begin() + q0, todo.begin() + q0 + nk), X, Aop, Gop);
         S.t_ortho += now() - t0;
         if (nw <= Nv) rebuild_from(sig);       // P holds every vector: put the new ones in
         t0 = now();
@@ -1290,6 +1327,7 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
           lam = l2;
           eps = e2;
           rr_tail(L);
+          ag_valid = false;
           S.t_rq += now() - t0;
           if (nw <= Nv) rebuild_from({0.0});
         }

@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__res
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);          // [12][bvol]
   __shared__ double red[3 * 16];
-  const int B = blocks[blockIdx.x];
+  const int B = blocks[xcd_tile(blockIdx.x, gridDim.x)];
   const int k = blockIdx.y;
   const int t = threadIdx.x;
   const bool active = t < g.bvol;
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(256 * R) k_sap_colour_lds(Geom g, const c64 *_
   __shared__ double red[R][4][3];
   const int bv = g.bvol;
   const int tpr = ((bv + 63) / 64) * 64;           // threads per right-hand side
-  const int B = blocks[blockIdx.x];
+  const int B = blocks[xcd_tile(blockIdx.x, gridDim.x)];
   const int t = threadIdx.x;
   const int r = t / tpr, l = t - r * tpr;
   const int k = blockIdx.y * R + r;

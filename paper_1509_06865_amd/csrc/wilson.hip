@@ -14,7 +14,7 @@ template <typename T, int MODE, int R>
 __global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restrict__ U,
                                                 const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
                                                 const cplx<T> *__restrict__ bin, T m0, Shifts sig, int nrhs) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int k0 = blockIdx.y * R;
   const int nr = (nrhs - k0 < R) ? nrhs - k0 : R;      // same for the whole launch row
@@ -71,7 +71,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__restrict__ U,
                                                       const cplx<T> *__restrict__ xin, long long xstride,
                                                       cplx<T> *__restrict__ parts, T m0, const int *half_dev) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int j = blockIdx.y;
   const int half = half_dev[j];

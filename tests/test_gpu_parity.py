@@ -100,15 +100,16 @@ def test_q_apply_full_size_sampled_sites():
     assert relmax(host(y32[0])[:, sites], ref) < 2e-6
 
 
-def test_coarse_apply_many_sites():
-    # 8192 coarse sites: the all-rhs-per-workgroup coarse kernel
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-6)], ids=["fp64", "fp32"])
+def test_coarse_apply_many_sites(prec, tol):
+    # 8192 coarse sites: the all-rhs-per-workgroup coarse kernel (FP64 or FP32)
     dims, agg = (16, 16, 16, 32), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 31)
     lat = Lattice(dims, 1)
     from paper_1509_06865_amd import MGParams
     c = _ctx(dims, 1)
     c.mg_setup(dev(U), -0.15, agg, dev(lqsynth.gaussian_spinors(4, dims, 32)),
-               MGParams(precision=0, n_setup=0, n_init=1))
+               MGParams(precision=prec, n_setup=0, n_init=1))
     P = host(c.get_interp())
     ag = M.Aggregation(lat, agg)
     Qc = M.coarse_operator(WilsonOp(U, -0.15, lat), ag, P)
@@ -119,7 +120,31 @@ def test_coarse_apply_many_sites():
     sig = [0.02 * k for k in range(nr)]
     y = host(c.coarse_apply(sig, dev(x)))
     ref = np.stack([M.coarse_apply(Qc, ag, x[k], sig[k]) for k in range(nr)])
-    assert relmax(y, ref) < 1e-12
+    assert relmax(y, ref) < tol
+
+
+def test_coarse_apply_galerkin_identity_full_blocks():
+    # 4096 coarse sites with 48 x 48 blocks (Nv = 24, the benchmark's block
+    # size), mixed precision: the coarse apply equals P^dag (Q - sigma) P x,
+    # the Galerkin identity of sec. 2, formed from the prolongation, the FP64
+    # Q apply and the restriction (each pinned to the oracle on small cases).
+    dims, agg = (16, 16, 16, 16), (2, 2, 2, 2)
+    U = lqsynth.gauge_field(dims, 0.25, 41)
+    from paper_1509_06865_amd import MGParams
+    c = _ctx(dims, 1)
+    Ud = dev(U)
+    c.mg_setup(Ud, -0.15, agg, dev(lqsynth.gaussian_spinors(24, dims, 42)),
+               MGParams(precision=1, n_setup=0, n_init=1))
+    nA = 8 ** 3 * 8
+    rng = np.random.default_rng(43)
+    nr = 9
+    x = rng.standard_normal((nr, nA, 48)) + 1j * rng.standard_normal((nr, nA, 48))
+    sig = [0.03 * k - 0.1 for k in range(nr)]
+    y = host(c.coarse_apply(sig, dev(x)))
+    for k in (0, 4, 8):
+        f = c.prolong(dev(x[k:k + 1]))
+        ref = host(c.restrict(c.q_apply(Ud, -0.15, f)))[0] - sig[k] * x[k]
+        assert relmax(y[k], ref) < 2e-5
 
 
 @pytest.mark.parametrize("nb,nw,n", [(1, 1, 7), (17, 5, 1000), (100, 16, 4096 * 3 + 29), (192, 16, 300)])
