@@ -24,6 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time for lowest-100 eigenpairs of Q at 32^3x64, tol 1e-10; Dirac-apply HBM GB/s"
+DEFAULT_CLASS = "sap"          # the kernel class with the largest share of the step's device time
+# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE passes (scaled by a
+# plain copy of known size), by kernel class; None until measured for the
+# current kernel source
+TRAFFIC = {}
 HBM_PEAK_GBS = 8000.0
 
 # Workloads: lattice, field, aggregation, Nv, N_eig, tolerance.  Masses come
@@ -102,26 +107,61 @@ def cpu_baseline(U_host, m0, dims, t_bc, x_host, n_outer):
                       f"and orthogonalisation are not counted"}
 
 
+# kernel classes of the library's timer (paper_1509_06865_amd.KT_*) and how
+# their algorithmic bytes are counted
+KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
+          "sap": (1, "SAP colour pass k_sap_colour_lds (links once + r, z in, z out per field)"),
+          "restrict": (2, "restriction k_restrict (P once + fields + coarse out)"),
+          "prolong": (3, "prolongation k_prolong"),
+          "coarse": (4, "coarse apply k_coarse_apply_multi (5 blocks per site once + x, y)"),
+          "gram": (5, "Gram products k_gram (E and W once)"),
+          "combine": (6, "basis combination k_combine")}
+
+
 def kernel_only(args):
-    """Launch only the roofline kernel (FP64 q_apply on the workload's lattice)
-    and a plain device copy of known size, for hardware-counter passes."""
+    """Launch only the kernels of one class on the workload's lattice, plus a
+    plain device copy of known size (12 V complex128 read and written), for
+    hardware-counter passes."""
     import torch
     import lqsynth
-    from paper_1509_06865_amd import Context
-    gold = load_golden(WORKLOADS[args.workload]["golden"])
-    dims, t_bc = tuple(gold["dims"]), gold["t_bc"]
+    from paper_1509_06865_amd import Context, MGParams
+    wl = WORKLOADS[args.workload]
+    gold = load_golden(wl["golden"])
+    dims, t_bc, m0 = tuple(gold["dims"]), gold["t_bc"], gold["m0"]
     V = int(np.prod(dims))
     U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
-    x = device_gaussian(1, dims, gold["field_seed"] + 3, torch)
     ctx = Context(dims, t_bc)
-    t = time_q_apply(ctx, U, gold["m0"], x, 10, torch)
+    cls = args.roofline_class
+    if cls == "wilson":
+        x = device_gaussian(1, dims, gold["field_seed"] + 3, torch)
+        t = time_q_apply(ctx, U, m0, x, 10, torch)
+        log(f"kernel-only: q_apply FP64 {t * 1e3:.3f} ms ({960.0 * V / t / 1e9:.0f} GB/s algorithmic)")
+    else:
+        tv0 = device_gaussian(wl["nv"], dims, gold["field_seed"] + 1, torch)
+        ctx.mg_setup(U, m0, wl["agg"], tv0, MGParams(precision=1, n_setup=0, n_init=1))
+        del tv0
+        nr = 8
+        r = device_gaussian(nr, dims, gold["field_seed"] + 4, torch)
+        sig = [0.01 * k for k in range(nr)]
+        for _ in range(3):
+            if cls == "sap":
+                ctx.smooth(sig, r, 1)
+            elif cls in ("restrict", "prolong", "coarse"):
+                c = ctx.restrict(r)
+                if cls == "coarse":
+                    ctx.coarse_apply(sig, c)
+                if cls == "prolong":
+                    ctx.prolong(c)
+            else:
+                ctx.cycle(sig, r)
+        torch.cuda.synchronize()
+        log(f"kernel-only: class {cls}, 3 passes over {nr} fields")
     a = torch.empty(12 * V * 2, dtype=torch.float64, device="cuda").normal_()
     b = torch.empty_like(a)
     for _ in range(10):
         b.copy_(a)
     torch.cuda.synchronize()
-    log(f"kernel-only: q_apply FP64 {t * 1e3:.3f} ms ({960.0 * V / t / 1e9:.0f} GB/s algorithmic); "
-        f"copy of {a.numel() * 8} bytes x10")
+    log(f"kernel-only: copy of {a.numel() * 8} bytes x10")
 
 
 def main():
@@ -137,7 +177,9 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=40)
     ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
     ap.add_argument("--kernel-only", action="store_true",
-                    help="run only the roofline kernel and a reference copy (for counter passes)")
+                    help="run only the roofline kernel class and a reference copy (for counter passes)")
+    ap.add_argument("--roofline-class", default=DEFAULT_CLASS, choices=sorted(KCLASS),
+                    help="kernel class timed live for the roofline object (default: the step's dominant one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -197,6 +239,8 @@ def main():
         step()
         log(f"warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
+    from paper_1509_06865_amd import kernel_timer_read, kernel_timer_start
+    kernel_timer_start(KCLASS[args.roofline_class][0])
     times, setups = [], []
     for s in range(args.steps):
         torch.cuda.synchronize()
@@ -209,6 +253,11 @@ def main():
         log(f"step {s + 1}/{args.steps}: {b - a:.2f} s (setup {t_setup - a:.2f} s), converged {info['converged']}, "
             f"sweeps {info['sweeps']}, solves {info['solves']}, fgmres its {info['fgmres_iters']}")
     T = max(times)
+    k_launches, k_ms, k_bytes = kernel_timer_read()
+    kernel_timer_start(-1)
+    k_gbs = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    log(f"roofline class {args.roofline_class}: {k_launches} launches, {k_ms / max(k_launches, 1):.4f} ms avg, "
+        f"{k_gbs:.0f} GB/s algorithmic")
     out = {
         "metric": METRIC, "value": round(T, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * T, 1), "higher_is_better": False, "scaling": "weak",
@@ -223,9 +272,11 @@ def main():
                    "fgmres_iters": info["fgmres_iters"],
                    "phase_s": {k: round(info[k], 3) for k in ("t_solve", "t_ortho", "t_rebuild", "t_rq")},
                    "dirac_apply_gbs": {"fp64": round(gbs64, 1), "fp32": round(gbs32, 1)}},
-        "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_wilson<double> (q_apply FP64), 960 B/site algorithmic"},
+        "roofline": {"bound": "hbm", "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(args.roofline_class),
+                     "kernel": KCLASS[args.roofline_class][1], "launches": k_launches,
+                     "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
+                     "bytes_per_launch": round(k_bytes / max(k_launches, 1))},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle Q apply on the host)")

@@ -167,6 +167,23 @@ int rqi_lowmodes(lq_ctx *ctx, int n_eig, double tol, double *lambda,
 int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
                       long long n, lq_c128 *out);
 
+/* ---- kernel timing (measurement of the hot kernels against the roofline) -- */
+/* Kernel classes: 0 Wilson stencil (q_apply and the solves), 1 SAP colour
+ * passes, 2 restriction, 3 prolongation, 4 coarse operator apply, 5 Gram
+ * products, 6 basis combinations; -1 switches timing off. */
+enum { LQ_KT_OFF = -1, LQ_KT_WILSON = 0, LQ_KT_SAP = 1, LQ_KT_RESTRICT = 2, LQ_KT_PROLONG = 3,
+       LQ_KT_COARSE = 4, LQ_KT_GRAM = 5, LQ_KT_COMBINE = 6 };
+/* Start timing one kernel class (process-wide, all contexts; clears earlier
+ * totals).  While on, every launch of the class records a pair of HIP events
+ * on the stream it is launched on and adds its algorithmic bytes (the data it
+ * must move at least: every operand read once, every result written once).
+ * Not thread-safe.  Errors: LQ_ERR_ARG for an unknown class. */
+int lq_kernel_timer_start(int kind);
+/* Launches timed since the last start, the sum of their device durations in
+ * milliseconds and of their algorithmic bytes; waits for the recorded events.
+ * Any argument may be NULL.  Errors: LQ_ERR_HIP. */
+int lq_kernel_timer_read(long long *launches, double *ms_total, double *bytes_total);
+
 /* ---- inspection of the hierarchy (parity tests; sec. 2 objects) ---------- */
 /* Number of test vectors Nv and aggregates nA of the current hierarchy. */
 int mg_info(lq_ctx *ctx, int *nv, int *n_agg);

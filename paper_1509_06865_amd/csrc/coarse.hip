@@ -154,6 +154,9 @@ __global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T
 template <typename T>
 void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig,
                          int nrhs, bool g5form, hipStream_t st) {
+  // algorithmic bytes: the 5 stored blocks per site once, x in and y out per field
+  KTimerScope kt(KT_COARSE, st,
+                 ((double)cg.nA * 5 * cg.n2 * cg.n2 + 2.0 * nrhs * cg.nA * cg.n2) * sizeof(cplx<T>));
   // Few coarse sites (< 1024): one wave per (site, rhs) keeps the GPU busy;
   // many sites: one workgroup per site, operator blocks read once for all rhs.
   if (nrhs >= 4 && cg.n2 <= 64 && cg.nA >= 1024) {

@@ -167,6 +167,7 @@ void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W
   nchunks = (n + per - 1) / per;
   const int nmt = (nb + 15) / 16;
   double *part = reinterpret_cast<double *>(scratch);
+  KTimerScope kt(KT_GRAM, st, (double)(nb + nw) * n * sizeof(c128));
   if (nw <= 8)
     hipLaunchKernelGGL((k_gram<1>), dim3((unsigned)nchunks), dim3(64 * nmt), 0, st, nb, E, estride, nw, W, wstride,
                        n, per, part);
@@ -184,6 +185,7 @@ void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128
   if (nb <= 0 || nw <= 0) return;
   if (nb > 192 || nw > 16) throw HipError(hipErrorInvalidValue, "launch_combine: nb <= 192 and nw <= 16", __FILE__, __LINE__);
   const dim3 grid(blocks_for(n, 256)), block(256);
+  KTimerScope kt(KT_COMBINE, st, (double)(nb + nw * (accumulate ? 2 : 1)) * n * sizeof(c128));
   if (nw == 8)
     hipLaunchKernelGGL((k_combine<8, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
   else if (nw == 16)

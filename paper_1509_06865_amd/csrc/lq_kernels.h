@@ -3,6 +3,7 @@
 // asynchronous on the given stream.
 #pragma once
 #include "lq_common.h"
+#include "lq_ktimer.h"
 
 namespace lq {
 

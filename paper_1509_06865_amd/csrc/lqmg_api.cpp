@@ -1302,9 +1302,14 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         S.t_rq += now() - t0;
         if (verbose()) {
           int itmax = 0;
-          for (int q = 0; q < nk; ++q) itmax = std::max(itmax, its[q]);
-          std::fprintf(stderr, "[lqmg]   sweep %d block at %zu: %d solves, max fgmres its %d, coarse its %d\n",
-                       S.sweeps + 1, q0, nk, itmax, c->coarse_iters);
+          double rmax = 0, rmin = 1e300;
+          for (int q = 0; q < nk; ++q) {
+            itmax = std::max(itmax, its[q]);
+            rmax = std::max(rmax, rr[q]);
+            rmin = std::min(rmin, rr[q]);
+          }
+          std::fprintf(stderr, "[lqmg]   sweep %d block at %zu: %d solves, max fgmres its %d, relres %.1e..%.1e, "
+                       "coarse its %d\n", S.sweeps + 1, q0, nk, itmax, rmin, rmax, c->coarse_iters);
           std::fflush(stderr);
         }
       }
@@ -1340,9 +1345,20 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
           nconv += eps[i] <= tol;
           emax = std::max(emax, eps[i]);
         }
-        std::fprintf(stderr, "[lqmg] rqi sweep %d: %d/%d converged, max eps %.3e, solves %d, fgmres its %d, "
-                     "t solve %.2fs ortho %.2fs rebuild %.2fs rq %.2fs\n", S.sweeps, nconv, nw, emax, S.solves,
-                     S.fgmres_iters, S.t_solve, S.t_ortho, S.t_rebuild, S.t_rq);
+        // the n_eig wanted (smallest |lambda|): how many have converged, worst residual
+        std::vector<int> o(nw);
+        for (int i = 0; i < nw; ++i) o[i] = i;
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return std::fabs(lam[a]) < std::fabs(lam[b]); });
+        int wconv = 0;
+        double wmax = 0;
+        for (int q = 0; q < n_eig; ++q) {
+          wconv += eps[o[q]] <= tol;
+          wmax = std::max(wmax, eps[o[q]]);
+        }
+        std::fprintf(stderr, "[lqmg] rqi sweep %d: %d/%d converged (wanted %d/%d, max eps %.2e), max eps %.3e, "
+                     "solves %d, fgmres its %d, t solve %.2fs ortho %.2fs rebuild %.2fs rq %.2fs\n", S.sweeps,
+                     nconv, nw, wconv, n_eig, wmax, emax, S.solves, S.fgmres_iters, S.t_solve, S.t_ortho,
+                     S.t_rebuild, S.t_rq);
         std::fflush(stderr);
       }
     }

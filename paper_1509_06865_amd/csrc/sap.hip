@@ -276,6 +276,8 @@ void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T
                        int nblocks, double m0, const Shifts &sig, int nrhs, int n_mr, hipStream_t st) {
   if (nblocks <= 0 || nrhs <= 0) return;
   const int threads = ((g.bvol + 63) / 64) * 64;
+  // algorithmic bytes: the colour's links once; per field r, z in and z out
+  KTimerScope kt(KT_SAP, st, (double)nblocks * g.bvol * (36.0 + 36.0 * nrhs) * sizeof(cplx<T>));
   if constexpr (sizeof(T) == 4) {
     if (g.bvol > kSapMaxSites) throw HipError(hipErrorInvalidValue, "SAP blocks hold at most 256 sites", __FILE__, __LINE__);
     constexpr int R = 2;

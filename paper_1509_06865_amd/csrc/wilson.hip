@@ -131,6 +131,9 @@ void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y
                    double m0, const Shifts &sig, int nrhs, int mode, hipStream_t st) {
   if (nrhs <= 0) return;
   constexpr int R = wilson_group<T>();
+  // algorithmic bytes: links once, each field in and out (and b when forming residuals)
+  KTimerScope kt(KT_WILSON, st,
+                 (double)g.V * (36.0 + nrhs * (mode == W_RESID ? 36.0 : 24.0)) * sizeof(cplx<T>));
   if (nrhs == 1) {
     const dim3 grid(blocks_for(g.V, 256), 1);
     if (mode == W_QSHIFT)

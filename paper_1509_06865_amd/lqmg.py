@@ -22,7 +22,11 @@ PREC_FP64, PREC_MIXED = 0, 1
 SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
-            "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products"]
+            "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
+            "lq_kernel_timer_start", "lq_kernel_timer_read"]
+
+# kernel classes of lq_kernel_timer_start
+KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
 
 
 class LQError(RuntimeError):
@@ -119,6 +123,8 @@ def load():
         "mg_smooth": (i, [vp, i, dp, vp, vp, i]),
         "mg_cycle": (i, [vp, i, dp, vp, vp]),
         "lq_inner_products": (i, [vp, i, vp, i, vp, C.c_longlong, vp]),
+        "lq_kernel_timer_start": (i, [i]),
+        "lq_kernel_timer_read": (i, [C.POINTER(C.c_longlong), dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -264,3 +270,19 @@ class Context:
         z = torch.empty_like(r)
         self._check(self.lib.mg_cycle(self.h, r.shape[0], _dbl(sigma), _ptr(r), _ptr(z)))
         return z
+
+
+def kernel_timer_start(kind: int):
+    """Time every launch of one kernel class from now on (-1: off)."""
+    rc = load().lq_kernel_timer_start(int(kind))
+    if rc != 0:
+        raise LQError(rc, "lq_kernel_timer_start: unknown kernel class")
+
+
+def kernel_timer_read():
+    """(launches, total device ms, total algorithmic bytes) since the last start."""
+    n, ms, by = C.c_longlong(), C.c_double(), C.c_double()
+    rc = load().lq_kernel_timer_read(C.byref(n), C.byref(ms), C.byref(by))
+    if rc != 0:
+        raise LQError(rc, "lq_kernel_timer_read failed")
+    return n.value, ms.value, by.value

@@ -113,7 +113,8 @@ def test_coarse_apply_many_sites(prec, tol):
     P = host(c.get_interp())
     ag = M.Aggregation(lat, agg)
     Qc = M.coarse_operator(WilsonOp(U, -0.15, lat), ag, P)
-    assert relmax(host(c.get_coarse()), Qc[:, :5]) < 1e-12
+    # in mixed precision the stored Q_c is the FP32 Galerkin product
+    assert relmax(host(c.get_coarse()), Qc[:, :5]) < (1e-12 if prec == 0 else 1e-6)
     rng = np.random.default_rng(33)
     nr = 11
     x = rng.standard_normal((nr, ag.nA, 8)) + 1j * rng.standard_normal((nr, ag.nA, 8))
