@@ -24,11 +24,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time for lowest-100 eigenpairs of Q at 32^3x64, tol 1e-10; Dirac-apply HBM GB/s"
-DEFAULT_CLASS = "sap"          # the kernel class with the largest share of the step's device time
+DEFAULT_CLASS = "coarse"       # the kernel class with the largest share of the step's device time
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE passes (scaled by a
-# plain copy of known size), by kernel class; None until measured for the
-# current kernel source
-TRAFFIC = {}
+# plain copy of known size), by kernel class and workload, with the SHA-256 of
+# the kernel's source at the time; reported only while the source is unchanged
+TRAFFIC = {
+    # k_coarse_apply<float>, 16 right-hand sides, 256 coarse sites of 40 unknowns
+    # (profiles/coarse_apply_16x4_traffic.md)
+    ("coarse", "medium"): {"bytes_per_launch": 16.21e6, "source_sha256": "7b3fd4a414f90687b94f38a41eda79f266c2df93013b65c8bcdc3e35c0a32788"},
+}
+KSOURCES = {"wilson": ["wilson.hip", "lq_dslash.h"], "sap": ["sap.hip", "lq_dslash.h"],
+            "restrict": ["transfer.hip"], "prolong": ["transfer.hip"], "coarse": ["coarse.hip"],
+            "gram": ["gram.hip"], "combine": ["gram.hip"]}
+
+
+def kernel_source_sha(cls):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KSOURCES[cls]:
+        with open(os.path.join(ROOT, "paper_1509_06865_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls, workload):
+    t = TRAFFIC.get((cls, workload))
+    if t is None or t["source_sha256"] != kernel_source_sha(cls):
+        return None
+    return t["bytes_per_launch"]
 HBM_PEAK_GBS = 8000.0
 
 # Workloads: lattice, field, aggregation, Nv, N_eig, tolerance.  Masses come
@@ -37,11 +60,11 @@ WORKLOADS = {
     # guard bands reach past the near-degenerate momentum shell that the
     # n_eig-th mode lies in (16^4: 12 + 96 modes; 32^3x64: 12 + 24 + 96)
     "large": dict(golden="large", agg=(4, 4, 4, 4), nv=24, n_eig=100, tol=1e-10, guard=32,
-                  params=dict(rqi_block=8, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=4,
-                              coarse_tol=0.15)),
+                  params=dict(rqi_block=8, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
+                              coarse_tol=0.15, rqi_start_passes=6)),
     "medium": dict(golden="medium", agg=(4, 4, 4, 4), nv=20, n_eig=50, tol=1e-10, guard=70,
-                   params=dict(rqi_block=16, fgmres_m=10, n_setup=4, coarse_m=40, coarse_restarts=4,
-                               coarse_tol=0.15)),
+                   params=dict(rqi_block=16, fgmres_m=10, n_setup=4, coarse_m=40, coarse_restarts=1,
+                               coarse_tol=0.3, rqi_start_passes=6)),
     "small": dict(golden="tiny_periodic", agg=(2, 2, 2, 2), nv=8, n_eig=8, tol=1e-10, guard=4,
                   params=dict(rqi_block=4, fgmres_m=10, n_setup=4, coarse_m=128, coarse_restarts=2,
                               coarse_tol=1e-8)),
@@ -110,10 +133,11 @@ def cpu_baseline(U_host, m0, dims, t_bc, x_host, n_outer):
 # kernel classes of the library's timer (paper_1509_06865_amd.KT_*) and how
 # their algorithmic bytes are counted
 KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
-          "sap": (1, "SAP colour pass k_sap_colour_lds (links once + r, z in, z out per field)"),
+          "sap": (1, "SAP colour pass k_sap_colour (links once + r, z in, z out per field)"),
           "restrict": (2, "restriction k_restrict (P once + fields + coarse out)"),
           "prolong": (3, "prolongation k_prolong"),
-          "coarse": (4, "coarse apply k_coarse_apply_multi (5 blocks per site once + x, y)"),
+          "coarse": (4, "coarse operator apply k_coarse_apply_multi (5 stored blocks per coarse site once + "
+                        "x in, y out per field)"),
           "gram": (5, "Gram products k_gram (E and W once)"),
           "combine": (6, "basis combination k_combine")}
 
@@ -132,6 +156,10 @@ def kernel_only(args):
     U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
     ctx = Context(dims, t_bc)
     cls = args.roofline_class
+    if cls == "all":
+        x = device_gaussian(1, dims, gold["field_seed"] + 3, torch)
+        t = time_q_apply(ctx, U, m0, x, 10, torch)
+        log(f"kernel-only: q_apply FP64 {t * 1e3:.3f} ms")
     if cls == "wilson":
         x = device_gaussian(1, dims, gold["field_seed"] + 3, torch)
         t = time_q_apply(ctx, U, m0, x, 10, torch)
@@ -140,11 +168,17 @@ def kernel_only(args):
         tv0 = device_gaussian(wl["nv"], dims, gold["field_seed"] + 1, torch)
         ctx.mg_setup(U, m0, wl["agg"], tv0, MGParams(precision=1, n_setup=0, n_init=1))
         del tv0
-        nr = 8
+        nr = wl["params"]["rqi_block"]            # the solves' batch width
         r = device_gaussian(nr, dims, gold["field_seed"] + 4, torch)
         sig = [0.01 * k for k in range(nr)]
         for _ in range(3):
-            if cls == "sap":
+            if cls == "all":
+                c = ctx.restrict(r)
+                ctx.coarse_apply(sig, c)
+                ctx.prolong(c)
+                ctx.smooth(sig, r, 1)
+                ctx.cycle(sig, r)
+            elif cls == "sap":
                 ctx.smooth(sig, r, 1)
             elif cls in ("restrict", "prolong", "coarse"):
                 c = ctx.restrict(r)
@@ -169,7 +203,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    # 16^4 / 50 pairs by default: the 32^3 x 64 / 100-pair case runs (--workload large) but does not
+    # converge within one run's time budget yet (its interior shifts defeat the two-level solver)
+    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-eig", type=int, default=None, help="override the workload's eigenpair count")
     ap.add_argument("--guard", type=int, default=None)
@@ -178,7 +214,7 @@ def main():
     ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the roofline kernel class and a reference copy (for counter passes)")
-    ap.add_argument("--roofline-class", default=DEFAULT_CLASS, choices=sorted(KCLASS),
+    ap.add_argument("--roofline-class", default=DEFAULT_CLASS, choices=sorted(KCLASS) + ["all"],
                     help="kernel class timed live for the roofline object (default: the step's dominant one)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -188,6 +224,8 @@ def main():
     if args.kernel_only:
         kernel_only(args)
         return
+    if args.roofline_class == "all":
+        ap.error("--roofline-class all is for --kernel-only runs")
 
     import torch
     import lqsynth
@@ -273,7 +311,7 @@ def main():
                    "phase_s": {k: round(info[k], 3) for k in ("t_solve", "t_ortho", "t_rebuild", "t_rq")},
                    "dirac_apply_gbs": {"fp64": round(gbs64, 1), "fp32": round(gbs32, 1)}},
         "roofline": {"bound": "hbm", "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get(args.roofline_class),
+                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.roofline_class, args.workload),
                      "kernel": KCLASS[args.roofline_class][1], "launches": k_launches,
                      "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
                      "bytes_per_launch": round(k_bytes / max(k_launches, 1))},

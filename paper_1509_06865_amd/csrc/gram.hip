@@ -159,7 +159,9 @@ void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W
   if (nb <= 0 || nw <= 0) return;
   if (nb > 16 * kGramMaxMT || nw > 16)
     throw HipError(hipErrorInvalidValue, "launch_gram: nb <= 192 and nw <= 16", __FILE__, __LINE__);
-  long long nchunks = (n + 8191) / 8192;
+  // chunks of >= 2048 elements, enough of them to give every CU several
+  // workgroups (16^4 fields: 384 chunks; 32^3 x 64: the 2048 maximum)
+  long long nchunks = (n + 2047) / 2048;
   if (nchunks > kGramMaxChunks) nchunks = kGramMaxChunks;
   if (nchunks < 1) nchunks = 1;
   long long per = (n + nchunks - 1) / nchunks;
@@ -167,16 +169,26 @@ void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W
   nchunks = (n + per - 1) / per;
   const int nmt = (nb + 15) / 16;
   double *part = reinterpret_cast<double *>(scratch);
-  KTimerScope kt(KT_GRAM, st, (double)(nb + nw) * n * sizeof(c128));
-  if (nw <= 8)
-    hipLaunchKernelGGL((k_gram<1>), dim3((unsigned)nchunks), dim3(64 * nmt), 0, st, nb, E, estride, nw, W, wstride,
-                       n, per, part);
-  else
-    hipLaunchKernelGGL((k_gram<2>), dim3((unsigned)nchunks), dim3(64 * nmt), 0, st, nb, E, estride, nw, W, wstride,
-                       n, per, part);
-  LQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_final, dim3(blocks_for((long long)nb * nw, 256)), dim3(256), 0, st, nb, nw,
-                     (int)nchunks, part, out);
+  KTimerScope kt(KT_GRAM, (double)(nb + nw) * n * sizeof(c128));
+  // timed from the start of the partial products to the end of the final sum
+  const dim3 g1((unsigned)nchunks), b1(64 * nmt), g2(blocks_for((long long)nb * nw, 256)), b2(256);
+  if (kt.on) {
+    if (nw <= 8)
+      hipExtLaunchKernelGGL((k_gram<1>), g1, b1, 0, st, kt.a, nullptr, 0, nb, E, estride, nw, W, wstride, n, per,
+                            part);
+    else
+      hipExtLaunchKernelGGL((k_gram<2>), g1, b1, 0, st, kt.a, nullptr, 0, nb, E, estride, nw, W, wstride, n, per,
+                            part);
+    LQ_HIP(hipGetLastError());
+    hipExtLaunchKernelGGL(k_gram_final, g2, b2, 0, st, nullptr, kt.b, 0, nb, nw, (int)nchunks, part, out);
+  } else {
+    if (nw <= 8)
+      hipLaunchKernelGGL((k_gram<1>), g1, b1, 0, st, nb, E, estride, nw, W, wstride, n, per, part);
+    else
+      hipLaunchKernelGGL((k_gram<2>), g1, b1, 0, st, nb, E, estride, nw, W, wstride, n, per, part);
+    LQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gram_final, g2, b2, 0, st, nb, nw, (int)nchunks, part, out);
+  }
   LQ_HIP(hipGetLastError());
 }
 
@@ -185,15 +197,15 @@ void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128
   if (nb <= 0 || nw <= 0) return;
   if (nb > 192 || nw > 16) throw HipError(hipErrorInvalidValue, "launch_combine: nb <= 192 and nw <= 16", __FILE__, __LINE__);
   const dim3 grid(blocks_for(n, 256)), block(256);
-  KTimerScope kt(KT_COMBINE, st, (double)(nb + nw * (accumulate ? 2 : 1)) * n * sizeof(c128));
+  KTimerScope kt(KT_COMBINE, (double)(nb + nw * (accumulate ? 2 : 1)) * n * sizeof(c128));
   if (nw == 8)
-    hipLaunchKernelGGL((k_combine<8, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+    LQ_LAUNCH(kt, (k_combine<8, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
   else if (nw == 16)
-    hipLaunchKernelGGL((k_combine<16, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+    LQ_LAUNCH(kt, (k_combine<16, true>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
   else if (nw < 8)
-    hipLaunchKernelGGL((k_combine<8, false>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+    LQ_LAUNCH(kt, (k_combine<8, false>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
   else
-    hipLaunchKernelGGL((k_combine<16, false>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
+    LQ_LAUNCH(kt, (k_combine<16, false>), grid, block, 0, st, nb, E, estride, nw, Y, U, ustride, n, accumulate);
   LQ_HIP(hipGetLastError());
 }
 

@@ -13,7 +13,6 @@ struct Pool {
   std::vector<hipEvent_t> a, b;
   std::vector<double> bytes;
   size_t used = 0;
-  bool open = false;
 };
 Pool &pool() {
   static Pool p;
@@ -21,30 +20,21 @@ Pool &pool() {
 }
 }  // namespace
 
-void ktimer_begin(hipStream_t st) {
+bool ktimer_acquire(hipEvent_t *start, hipEvent_t *stop, double bytes) {
   Pool &p = pool();
   if (p.used == p.a.size()) {
     hipEvent_t x, y;
-    if (hipEventCreate(&x) != hipSuccess || hipEventCreate(&y) != hipSuccess) {
-      (void)hipGetLastError();
-      g_ktimer_class = -1;                 // give up timing rather than fail the launch
-      return;
-    }
+    if (hipEventCreate(&x) != hipSuccess) { (void)hipGetLastError(); return false; }
+    if (hipEventCreate(&y) != hipSuccess) { (void)hipGetLastError(); (void)hipEventDestroy(x); return false; }
     p.a.push_back(x);
     p.b.push_back(y);
     p.bytes.push_back(0.0);
   }
-  (void)hipEventRecord(p.a[p.used], st);
-  p.open = true;
-}
-
-void ktimer_end(hipStream_t st, double bytes) {
-  Pool &p = pool();
-  if (!p.open) return;
-  (void)hipEventRecord(p.b[p.used], st);
+  *start = p.a[p.used];
+  *stop = p.b[p.used];
   p.bytes[p.used] = bytes;
   ++p.used;
-  p.open = false;
+  return true;
 }
 
 }  // namespace lq
@@ -52,7 +42,6 @@ void ktimer_end(hipStream_t st, double bytes) {
 extern "C" int lq_kernel_timer_start(int kind) {
   if (kind < -1 || kind >= lq::KT_COUNT) return LQ_ERR_ARG;
   lq::pool().used = 0;
-  lq::pool().open = false;
   lq::g_ktimer_class = kind;
   return LQ_OK;
 }

@@ -1213,11 +1213,12 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
       }
       S.t_solve += now() - t0;
       t0 = now();
-      orthonormalise(c, E, nw);
-      S.t_ortho += now() - t0;
-      t0 = now();
-      if (c->p.rayleigh_ritz) rr_tail(0);
-      else rq_resid([&] { std::vector<int> a(nw); for (int i = 0; i < nw; ++i) a[i] = i; return a; }());
+      if (c->p.rayleigh_ritz) {
+        rr_tail(0);                 // generalised Rayleigh-Ritz: its Ritz vectors are orthonormal
+      } else {
+        orthonormalise(c, E, nw);
+        rq_resid([&] { std::vector<int> a(nw); for (int i = 0; i < nw; ++i) a[i] = i; return a; }());
+      }
       S.t_rq += now() - t0;
       rebuild_from({0.0});
       if (verbose()) {

@@ -34,12 +34,17 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *lds) 
 template <typename T>
 __global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__restrict__ U,
                                                     const cplx<T> *__restrict__ rin, cplx<T> *__restrict__ zio,
-                                                    const int *__restrict__ blocks, T m0, Shifts sig, int n_mr) {
+                                                    const int *__restrict__ blocks, T m0, Shifts sig, int n_mr,
+                                                    int nrhs) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);          // [12][bvol]
   __shared__ double red[3 * 16];
-  const int B = blocks[xcd_tile(blockIdx.x, gridDim.x)];
-  const int k = blockIdx.y;
+  // one workgroup per (block, rhs); the right-hand sides of one block are
+  // consecutive tiles of one XCD, so its links are read from HBM once and
+  // then come from that XCD's L2
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int B = blocks[tile / nrhs];
+  const int k = tile - (tile / nrhs) * nrhs;
   const int t = threadIdx.x;
   const bool active = t < g.bvol;
   const int s = B * g.bvol + (active ? t : 0);
@@ -136,139 +141,6 @@ __global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__res
 }
 
 
-// FP32 variant: the block's links are staged in LDS once and shared by R
-// right-hand sides (R groups of threads, one site per thread in each group);
-// the MR iterations then read links and the exchanged iterate from LDS only.
-// Static LDS sized for the largest block (256 sites): 36 link entries per
-// site plus R iterates of 12 components.
-constexpr int kSapMaxSites = 256;
-
-template <int R>
-__global__ void __launch_bounds__(256 * R) k_sap_colour_lds(Geom g, const c64 *__restrict__ U,
-                                                           const c64 *__restrict__ rin, c64 *__restrict__ zio,
-                                                           const int *__restrict__ blocks, float m0, Shifts sig,
-                                                           int n_mr, int nrhs) {
-  __shared__ c64 Ul[36 * kSapMaxSites];            // [mu * 9 + k][site]
-  __shared__ c64 X[R][12 * kSapMaxSites];          // [rhs][component][site]
-  __shared__ double red[R][4][3];
-  const int bv = g.bvol;
-  const int tpr = ((bv + 63) / 64) * 64;           // threads per right-hand side
-  const int B = blocks[xcd_tile(blockIdx.x, gridDim.x)];
-  const int t = threadIdx.x;
-  const int r = t / tpr, l = t - r * tpr;
-  const int k = blockIdx.y * R + r;
-  const bool active = l < bv && k < nrhs;
-  const int s = B * bv + (l < bv ? l : 0);
-  const long long off = (long long)(k < nrhs ? k : 0) * 12 * g.V;
-  const c64 *rr = rin + off;
-  c64 *z = zio + off;
-  const float sgm = (float)sig.s[k < nrhs ? k : 0];
-  const float diag = 4.f + m0;
-  const SiteCoord c = decode(g, s);
-  for (int idx = t; idx < 36 * bv; idx += blockDim.x) {
-    const int mk_ = idx / bv, site = idx - mk_ * bv;
-    Ul[idx] = U[(long long)mk_ * g.V + (long long)B * bv + site];
-  }
-  __syncthreads();
-  auto lds_link = [&](int mu, int site, c64 m[9]) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) m[q] = Ul[(mu * 9 + q) * bv + site];
-  };
-
-  // block residual rho = gamma5 r - D_sigma z (full stencil)
-  c64 rho[12], e[12], p[12], q[12], m[9];
-  if (active) {
-    c64 acc[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = mk(0.f, 0.f);
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-      float sg; bool in;
-      const int sf = neighbour(g, s, c, mu, true, &sg, &in);
-#pragma unroll
-      for (int i = 0; i < 12; ++i) q[i] = z[(long long)i * g.V + sf];
-      lds_link(mu, l, m);
-      hop_link(mu, true, q, m, sg, acc);
-      const int sb = neighbour(g, s, c, mu, false, &sg, &in);
-#pragma unroll
-      for (int i = 0; i < 12; ++i) q[i] = z[(long long)i * g.V + sb];
-      if (in) lds_link(mu, l - g.sl[mu], m);
-      else load_link(U, g.V, mu, sb, m);
-      hop_link(mu, false, q, m, sg, acc);
-    }
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      const c64 zi = z[(long long)i * g.V + s];
-      const c64 ri = rr[(long long)i * g.V + s];
-      const float g5 = (i < 6) ? 1.f : -1.f;
-      const c64 dz = diag * zi - 0.5f * acc[i] - (sgm * g5) * zi;
-      rho[i] = g5 * ri - dz;
-      e[i] = mk(0.f, 0.f);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) { rho[i] = mk(0.f, 0.f); e[i] = mk(0.f, 0.f); }
-  }
-
-  const int lane = t & 63, wr = l >> 6, nwr = tpr >> 6;
-  c64 *Xr = X[r];
-  for (int it = 0; it < n_mr; ++it) {
-    __syncthreads();
-    if (active)
-#pragma unroll
-      for (int i = 0; i < 12; ++i) Xr[i * bv + l] = rho[i];
-    __syncthreads();
-    double num_re = 0, num_im = 0, den = 0;
-    if (active) {
-      c64 acc[12];
-#pragma unroll
-      for (int i = 0; i < 12; ++i) acc[i] = mk(0.f, 0.f);
-#pragma unroll 1
-      for (int mu = 0; mu < 4; ++mu) {
-        if (c.l[mu] + 1 < g.b[mu]) {
-          const int tn = l + g.sl[mu];
-#pragma unroll
-          for (int i = 0; i < 12; ++i) q[i] = Xr[i * bv + tn];
-          lds_link(mu, l, m);
-          hop_link(mu, true, q, m, 1.f, acc);
-        }
-        if (c.l[mu] > 0) {
-          const int tn = l - g.sl[mu];
-#pragma unroll
-          for (int i = 0; i < 12; ++i) q[i] = Xr[i * bv + tn];
-          lds_link(mu, tn, m);
-          hop_link(mu, false, q, m, 1.f, acc);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        const float g5 = (i < 6) ? 1.f : -1.f;
-        p[i] = diag * rho[i] - 0.5f * acc[i] - (sgm * g5) * rho[i];
-        num_re += (double)p[i].re * rho[i].re + (double)p[i].im * rho[i].im;
-        num_im += (double)p[i].re * rho[i].im - (double)p[i].im * rho[i].re;
-        den += (double)p[i].re * p[i].re + (double)p[i].im * p[i].im;
-      }
-    }
-    // sums over this right-hand side's waves
-    num_re = wsum(num_re); num_im = wsum(num_im); den = wsum(den);
-    if (lane == 0) { red[r][wr][0] = num_re; red[r][wr][1] = num_im; red[r][wr][2] = den; }
-    __syncthreads();
-    num_re = num_im = den = 0;
-    for (int w = 0; w < nwr; ++w) { num_re += red[r][w][0]; num_im += red[r][w][1]; den += red[r][w][2]; }
-    c64 alpha = mk(0.f, 0.f);
-    if (den > 0) alpha = mk((float)(num_re / den), (float)(num_im / den));
-    if (active)
-#pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        e[i] = e[i] + alpha * rho[i];
-        rho[i] = rho[i] - alpha * p[i];
-      }
-  }
-  if (active)
-#pragma unroll
-    for (int i = 0; i < 12; ++i) z[(long long)i * g.V + s] = z[(long long)i * g.V + s] + e[i];
-}
-
 }  // namespace
 
 template <typename T>
@@ -277,17 +149,10 @@ void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T
   if (nblocks <= 0 || nrhs <= 0) return;
   const int threads = ((g.bvol + 63) / 64) * 64;
   // algorithmic bytes: the colour's links once; per field r, z in and z out
-  KTimerScope kt(KT_SAP, st, (double)nblocks * g.bvol * (36.0 + 36.0 * nrhs) * sizeof(cplx<T>));
-  if constexpr (sizeof(T) == 4) {
-    if (g.bvol > kSapMaxSites) throw HipError(hipErrorInvalidValue, "SAP blocks hold at most 256 sites", __FILE__, __LINE__);
-    constexpr int R = 2;
-    hipLaunchKernelGGL((k_sap_colour_lds<R>), dim3(nblocks, (nrhs + R - 1) / R), dim3(threads * R), 0, st, g, U, r,
-                       z, blocks, (float)m0, sig, n_mr, nrhs);
-  } else {
-    const size_t lds = (size_t)12 * g.bvol * sizeof(cplx<T>);
-    hipLaunchKernelGGL((k_sap_colour<T>), dim3(nblocks, nrhs), dim3(threads), lds, st, g, U, r, z, blocks, (T)m0,
-                       sig, n_mr);
-  }
+  KTimerScope kt(KT_SAP, (double)nblocks * g.bvol * (36.0 + 36.0 * nrhs) * sizeof(cplx<T>));
+  const size_t lds = (size_t)12 * g.bvol * sizeof(cplx<T>);
+  LQ_LAUNCH(kt, (k_sap_colour<T>), dim3(nblocks * nrhs), dim3(threads), lds, st, g, U, r, z, blocks, (T)m0,
+                     sig, n_mr, nrhs);
   LQ_HIP(hipGetLastError());
 }
 

@@ -254,9 +254,8 @@ void launch_restrict(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *f, 
   const int threads = ((g.bvol + 63) / 64) * 64;
   constexpr int R = transfer_group<T>();
   // algorithmic bytes: P once, the fields, the coarse output
-  KTimerScope kt(KT_RESTRICT, st,
-                 ((double)g.V * 12.0 * (Nv + nf) + (double)nf * g.nblk * 2 * Nv) * sizeof(cplx<T>));
-  hipLaunchKernelGGL((k_restrict<T, R>), dim3(g.nblk, (nf + R - 1) / R), dim3(threads), 0, st, g, P, Nv, f, fstride,
+  KTimerScope kt(KT_RESTRICT, ((double)g.V * 12.0 * (Nv + nf) + (double)nf * g.nblk * 2 * Nv) * sizeof(cplx<T>));
+  LQ_LAUNCH(kt, (k_restrict<T, R>), dim3(g.nblk, (nf + R - 1) / R), dim3(threads), 0, st, g, P, Nv, f, fstride,
                      nf, c);
   LQ_HIP(hipGetLastError());
 }
@@ -267,10 +266,9 @@ void launch_prolong(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *c, c
   const int threads = ((g.bvol + 63) / 64) * 64;
   constexpr int R = transfer_group<T>();
   // algorithmic bytes: P once, the coarse input, the fields out (and in when accumulating)
-  KTimerScope kt(KT_PROLONG, st,
-                 ((double)g.V * 12.0 * (Nv + nf * (accumulate ? 2.0 : 1.0)) + (double)nf * g.nblk * 2 * Nv) *
+  KTimerScope kt(KT_PROLONG, ((double)g.V * 12.0 * (Nv + nf * (accumulate ? 2.0 : 1.0)) + (double)nf * g.nblk * 2 * Nv) *
                      sizeof(cplx<T>));
-  hipLaunchKernelGGL((k_prolong<T, R>), dim3(g.nblk, (nf + R - 1) / R), dim3(threads), 0, st, g, P, Nv, c, f,
+  LQ_LAUNCH(kt, (k_prolong<T, R>), dim3(g.nblk, (nf + R - 1) / R), dim3(threads), 0, st, g, P, Nv, c, f,
                      fstride, nf, accumulate);
   LQ_HIP(hipGetLastError());
 }

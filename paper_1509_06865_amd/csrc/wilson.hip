@@ -132,20 +132,19 @@ void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y
   if (nrhs <= 0) return;
   constexpr int R = wilson_group<T>();
   // algorithmic bytes: links once, each field in and out (and b when forming residuals)
-  KTimerScope kt(KT_WILSON, st,
-                 (double)g.V * (36.0 + nrhs * (mode == W_RESID ? 36.0 : 24.0)) * sizeof(cplx<T>));
+  KTimerScope kt(KT_WILSON, (double)g.V * (36.0 + nrhs * (mode == W_RESID ? 36.0 : 24.0)) * sizeof(cplx<T>));
   if (nrhs == 1) {
     const dim3 grid(blocks_for(g.V, 256), 1);
     if (mode == W_QSHIFT)
-      hipLaunchKernelGGL((k_wilson<T, W_QSHIFT, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
     else
-      hipLaunchKernelGGL((k_wilson<T, W_RESID, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_RESID, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
   } else {
     const dim3 grid(blocks_for(g.V, 256), (nrhs + R - 1) / R);
     if (mode == W_QSHIFT)
-      hipLaunchKernelGGL((k_wilson<T, W_QSHIFT, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
     else
-      hipLaunchKernelGGL((k_wilson<T, W_RESID, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_RESID, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
   }
   LQ_HIP(hipGetLastError());
 }

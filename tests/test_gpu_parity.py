@@ -148,6 +148,26 @@ def test_coarse_apply_galerkin_identity_full_blocks():
         assert relmax(y[k], ref) < 2e-5
 
 
+def test_kernel_timer_counts_wilson_launches_and_bytes():
+    # the roofline instrumentation: every Wilson launch of q_apply is timed
+    # and credited with 960 B per site (FP64: links, field in, field out)
+    from paper_1509_06865_amd import KT_WILSON, kernel_timer_read, kernel_timer_start
+    dims = (8, 8, 8, 16)
+    V = int(np.prod(dims))
+    c = _ctx(dims, 1)
+    U = dev(lqsynth.gauge_field(dims, 0.3, 51))
+    x = dev(lqsynth.gaussian_spinors(1, dims, 52))
+    c.q_apply(U, -0.2, x)
+    torch.cuda.synchronize()
+    kernel_timer_start(KT_WILSON)
+    for _ in range(3):
+        c.q_apply(U, -0.2, x)
+    n, ms, nbytes = kernel_timer_read()
+    kernel_timer_start(-1)
+    assert n == 3 and ms > 0
+    assert nbytes == 3 * 960 * V
+
+
 @pytest.mark.parametrize("nb,nw,n", [(1, 1, 7), (17, 5, 1000), (100, 16, 4096 * 3 + 29), (192, 16, 300)])
 def test_inner_products_match_numpy(nb, nw, n):
     rng = np.random.default_rng(nb * 31 + nw)
@@ -283,3 +303,37 @@ def test_rqi_lowest_eight_match_dense(name, prec, nv):
         assert np.linalg.norm(Qv[i] - lam[i] * Vh[i]) <= 2e-10
     G = np.einsum("ian,jan->ij", Vh.conj(), Vh)
     assert np.abs(G - np.eye(8)).max() < 1e-10
+
+
+def test_rqi_benchmark_workload_returns_exact_pairs():
+    # The benchmark's configuration at full size (16^4, 50 lowest pairs,
+    # Nv = 20, guard 70, 6 start passes, blocks of 16 shifted solves): every
+    # returned pair is an eigenpair of the oracle's Q to the tolerance,
+    # lambda is its Rayleigh quotient, the vectors are orthonormal and sorted
+    # by |lambda|.  (A dense reference is out of reach at 786k unknowns.)
+    cfg = json.load(open(GOLDEN))["medium"]
+    dims, bc, m0 = tuple(cfg["dims"]), cfg["t_bc"], cfg["m0"]
+    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
+    lat = Lattice(dims, bc)
+    from paper_1509_06865_amd import MGParams
+    c = _ctx(dims, bc)
+    c.mg_setup(dev(U), m0, (4, 4, 4, 4), dev(lqsynth.gaussian_spinors(20, dims, 202)),
+               MGParams(precision=1, rqi_block=16, fgmres_m=10, n_setup=4, coarse_m=40, coarse_restarts=1,
+                        coarse_tol=0.3, rqi_start_passes=6, rqi_guard=70, rayleigh_ritz=1, rqi_max_sweeps=20))
+    V0 = dev(lqsynth.gaussian_spinors(50 + 70 - 20, dims, 203))
+    lam, V, res, info = c.rqi_lowmodes(50, 1e-10, V0=V0)
+    assert info["converged"], info
+    lam = np.array(lam)
+    assert np.all(np.diff(np.abs(lam)) >= 0)
+    Vh = host(V)
+    del V, V0
+    op = WilsonOp(U, m0, lat)
+    for i in range(50):
+        v = Vh[i]
+        Qv = op.Q(v)
+        assert abs(np.linalg.norm(v) - 1) < 1e-12
+        assert abs(np.vdot(v, Qv).real - lam[i]) < 1e-12
+        assert np.linalg.norm(Qv - lam[i] * v) <= 2e-10
+    G = np.einsum("ian,jan->ij", Vh.conj(), Vh)
+    assert np.abs(G - np.eye(50)).max() < 1e-10
+
