@@ -136,8 +136,8 @@ KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
           "sap": (1, "SAP colour pass k_sap_colour (links once + r, z in, z out per field)"),
           "restrict": (2, "restriction k_restrict (P once + fields + coarse out)"),
           "prolong": (3, "prolongation k_prolong"),
-          "coarse": (4, "coarse operator apply k_coarse_apply_multi (5 stored blocks per coarse site once + "
-                        "x in, y out per field)"),
+          "coarse": (4, "coarse operator apply k_coarse_apply (< 1024 coarse sites) / k_coarse_apply_multi "
+                        "(5 stored blocks per coarse site once + x in, y out per field)"),
           "gram": (5, "Gram products k_gram (E and W once)"),
           "combine": (6, "basis combination k_combine")}
 
