@@ -66,6 +66,86 @@ __global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restric
   }
 }
 
+// Canonical layout (one block), one field: each thread walks a column of up
+// to TC timeslices at one spatial site.  The forward t neighbour it loads is
+// the next site's own spinor, and the backward t hop into the next site,
+// (1 + gamma_t) U_t(n)^dag x(n), is formed from the link and spinor already in
+// registers and carried as a projected half spinor, so every spinor and t link
+// is read once per column.  Consecutive threads take consecutive spatial
+// sites (coalesced); column chunks are renumbered per XCD like the other
+// stencil launches.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wilson_tcol(Geom g, const cplx<T> *__restrict__ U,
+                                                     const cplx<T> *__restrict__ x, cplx<T> *__restrict__ y, T m0,
+                                                     int TC) {
+  const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
+  const int S3 = L0 * L1 * L2;
+  const int nchunk = (L3 + TC - 1) / TC;
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (col >= S3 * nchunk) return;
+  const int chunk = col / S3;
+  const int sp = col - chunk * S3;
+  const int t0 = chunk * TC, t1 = (t0 + TC < L3) ? t0 + TC : L3;
+  const long long V = g.V;
+  const int cx = sp % L0, cy = (sp / L0) % L1, cz = sp / (L0 * L1);
+  // spatial neighbours (periodic) of the column, forward and backward
+  int nf[3], nb[3];
+  nf[0] = (cx + 1 < L0) ? sp + 1 : sp - (L0 - 1);
+  nb[0] = (cx > 0) ? sp - 1 : sp + (L0 - 1);
+  nf[1] = (cy + 1 < L1) ? sp + L0 : sp - (L1 - 1) * L0;
+  nb[1] = (cy > 0) ? sp - L0 : sp + (L1 - 1) * L0;
+  nf[2] = (cz + 1 < L2) ? sp + L0 * L1 : sp - (L2 - 1) * L0 * L1;
+  nb[2] = (cz > 0) ? sp - L0 * L1 : sp + (L2 - 1) * L0 * L1;
+  const T tsign = (T)g.tbc;
+  cplx<T> xc[12], p[12], m[9], acc[12];
+  Half2<T> h, ub;
+  // backward t hop into t0, from t0 - 1 (boundary sign when t0 = 0)
+  {
+    const int tm = (t0 > 0) ? t0 - 1 : L3 - 1;
+    const int n = sp + tm * S3;
+    load_spinor(x, V, n, p);
+    load_link(U, V, 3, n, m);
+    project(3, (T)1, p, h);
+    link_mul(m, h, ub, true);
+  }
+  T ubsign = (t0 > 0) ? (T)1 : tsign;
+  load_spinor(x, V, sp + t0 * S3, xc);
+  const T diag = (T)4 + m0;
+  for (int t = t0; t < t1; ++t) {
+    const int n = sp + t * S3;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+    reconstruct(3, (T)1, ub, ubsign, acc);
+    // spatial hops
+#pragma unroll 1
+    for (int mu = 0; mu < 3; ++mu) {
+      const int f = nf[mu] + t * S3, b = nb[mu] + t * S3;
+      load_spinor(x, V, f, p);
+      load_link(U, V, mu, n, m);
+      hop_link(mu, true, p, m, (T)1, acc);
+      load_spinor(x, V, b, p);
+      load_link(U, V, mu, b, m);
+      hop_link(mu, false, p, m, (T)1, acc);
+    }
+    // forward t hop; its spinor is the next site's own
+    const bool wrap = (t + 1 == L3);
+    load_spinor(x, V, wrap ? sp : n + S3, p);
+    load_link(U, V, 3, n, m);
+    hop_link(3, true, p, m, wrap ? tsign : (T)1, acc);
+    // backward t hop into t + 1, carried
+    project(3, (T)1, xc, h);
+    link_mul(m, h, ub, true);
+    ubsign = (T)1;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      cplx<T> d = diag * xc[i] - (T)0.5 * acc[i];
+      if (i >= 6) d = -d;                        // gamma5
+      y[(long long)i * V + n] = d;
+      xc[i] = p[i];
+    }
+  }
+}
+
 // Parts of Q for the Galerkin product, per column field j.
 template <typename T>
 __global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__restrict__ U,
@@ -133,7 +213,11 @@ void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y
   constexpr int R = wilson_group<T>();
   // algorithmic bytes: links once, each field in and out (and b when forming residuals)
   KTimerScope kt(KT_WILSON, (double)g.V * (36.0 + nrhs * (mode == W_RESID ? 36.0 : 24.0)) * sizeof(cplx<T>));
-  if (nrhs == 1) {
+  if (nrhs == 1 && mode == W_QSHIFT && g.nblk == 1 && sig.s[0] == 0.0 && g.L[3] >= 2) {
+    constexpr int TC = 8;                      // timeslices per thread
+    const long long cols = (long long)g.L[0] * g.L[1] * g.L[2] * ((g.L[3] + TC - 1) / TC);
+    LQ_LAUNCH(kt, (k_wilson_tcol<T>), dim3(blocks_for(cols, 256)), dim3(256), 0, st, g, U, x, y, (T)m0, TC);
+  } else if (nrhs == 1) {
     const dim3 grid(blocks_for(g.V, 256), 1);
     if (mode == W_QSHIFT)
       LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);

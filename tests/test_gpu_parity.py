@@ -54,6 +54,9 @@ def test_q_apply_fp64_matches_oracle(dims, bc):
     y = host(c.q_apply(dev(U), -0.2, dev(x)))
     torch.cuda.synchronize()
     assert relmax(y, ref) < 1e-13
+    # one field: the timeslice-column kernel (partial columns when T % 8 != 0)
+    y1 = host(c.q_apply(dev(U), -0.2, dev(x[:1])))
+    assert relmax(y1, ref[:1]) < 1e-13
 
 
 @pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), 1), ((6, 4, 2, 10), -1)])
@@ -65,6 +68,8 @@ def test_q_apply_fp32_matches_oracle(dims, bc):
     c = _ctx(dims, bc)
     y = host(c.q_apply(dev(U, torch.complex64), 0.1, dev(x, torch.complex64)))
     assert relmax(y, ref) < 2e-6
+    y1 = host(c.q_apply(dev(U, torch.complex64), 0.1, dev(x[:1], torch.complex64)))
+    assert relmax(y1, ref[:1]) < 2e-6
 
 
 def test_q_apply_many_rhs_chunks():
