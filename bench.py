@@ -24,14 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time for lowest-100 eigenpairs of Q at 32^3x64, tol 1e-10; Dirac-apply HBM GB/s"
-DEFAULT_CLASS = "coarse"       # the kernel class with the largest share of the step's device time
+DEFAULT_CLASS = "sap"          # the kernel class with the largest share of the step's device time
 # HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE passes (scaled by a
 # plain copy of known size), by kernel class and workload, with the SHA-256 of
 # the kernel's source at the time; reported only while the source is unchanged
 TRAFFIC = {
+    # profiles/hbm_traffic_16x4.md: k_sap_colour<float>, one colour, 16 right-hand sides
+    ("sap", "medium"): {"bytes_per_launch": 279.64e6,
+                        "source_sha256": "44ec01ea24becf25890fc8e27ec951d7fe2cd303ca180135bc615e4f96b994c8"},
     # k_coarse_apply<float>, 16 right-hand sides, 256 coarse sites of 40 unknowns
-    # (profiles/coarse_apply_16x4_traffic.md)
-    ("coarse", "medium"): {"bytes_per_launch": 16.21e6, "source_sha256": "7b3fd4a414f90687b94f38a41eda79f266c2df93013b65c8bcdc3e35c0a32788"},
+    ("coarse", "medium"): {"bytes_per_launch": 16.22e6,
+                           "source_sha256": "7b3fd4a414f90687b94f38a41eda79f266c2df93013b65c8bcdc3e35c0a32788"},
 }
 KSOURCES = {"wilson": ["wilson.hip", "lq_dslash.h"], "sap": ["sap.hip", "lq_dslash.h"],
             "restrict": ["transfer.hip"], "prolong": ["transfer.hip"], "coarse": ["coarse.hip"],

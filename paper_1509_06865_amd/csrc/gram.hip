@@ -91,18 +91,29 @@ __global__ void __launch_bounds__(64 * kGramMaxMT) k_gram(int nb, const c128 *__
   }
 }
 
-// out[i][k] = sum over chunks of partial[chunk][i][k], fixed order
-__global__ void k_gram_final(int nb, int nw, int nchunks, const double *__restrict__ partial, c128 *__restrict__ out) {
-  const int ik = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ik >= nb * nw) return;
-  const int i = ik / nw, k = ik - i * nw;
+// out[i][k] = sum over chunks of partial[chunk][i][k], fixed order.  One
+// workgroup per row i: thread t adds column t % 16 over the chunks congruent
+// to t / 16 modulo 16 (coalesced 256-byte rows of partials), then the 16
+// group sums of a column are added in group order.
+__global__ void __launch_bounds__(256) k_gram_final(int nb, int nw, int nchunks, const double *__restrict__ partial,
+                                                    c128 *__restrict__ out) {
+  __shared__ double red[16][16][2];
+  const int i = blockIdx.x, t = threadIdx.x;
+  const int k = t & 15, grp = t >> 4;
   double re = 0, im = 0;
-  for (int c = 0; c < nchunks; ++c) {
+  for (int c = grp; c < nchunks; c += 16) {
     const double *v = partial + (((long long)c * nb + i) * 16 + k) * 2;
     re += v[0];
     im += v[1];
   }
-  out[ik] = c128{re, im};
+  red[grp][k][0] = re;
+  red[grp][k][1] = im;
+  __syncthreads();
+  if (t < nw) {
+    double sr = 0, si = 0;
+    for (int g = 0; g < 16; ++g) { sr += red[g][t][0]; si += red[g][t][1]; }
+    out[(long long)i * nw + t] = c128{sr, si};
+  }
 }
 
 // U_k[e] = (U_k[e] if acc) + sum_i Y[i][k] E_i[e], one thread per element.
@@ -159,9 +170,9 @@ void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W
   if (nb <= 0 || nw <= 0) return;
   if (nb > 16 * kGramMaxMT || nw > 16)
     throw HipError(hipErrorInvalidValue, "launch_gram: nb <= 192 and nw <= 16", __FILE__, __LINE__);
-  // chunks of >= 2048 elements, enough of them to give every CU several
-  // workgroups (16^4 fields: 384 chunks; 32^3 x 64: the 2048 maximum)
-  long long nchunks = (n + 2047) / 2048;
+  // chunks of >= 1024 elements, enough of them to give every CU several
+  // workgroups (16^4 fields: 768 chunks; 32^3 x 64: the 2048 maximum)
+  long long nchunks = (n + 1023) / 1024;
   if (nchunks > kGramMaxChunks) nchunks = kGramMaxChunks;
   if (nchunks < 1) nchunks = 1;
   long long per = (n + nchunks - 1) / nchunks;
@@ -171,7 +182,7 @@ void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W
   double *part = reinterpret_cast<double *>(scratch);
   KTimerScope kt(KT_GRAM, (double)(nb + nw) * n * sizeof(c128));
   // timed from the start of the partial products to the end of the final sum
-  const dim3 g1((unsigned)nchunks), b1(64 * nmt), g2(blocks_for((long long)nb * nw, 256)), b2(256);
+  const dim3 g1((unsigned)nchunks), b1(64 * nmt), g2(nb), b2(256);
   if (kt.on) {
     if (nw <= 8)
       hipExtLaunchKernelGGL((k_gram<1>), g1, b1, 0, st, kt.a, nullptr, 0, nb, E, estride, nw, W, wstride, n, per,

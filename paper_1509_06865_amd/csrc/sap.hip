@@ -14,21 +14,10 @@
 namespace lq {
 namespace {
 
-__device__ inline double wsum(double v) {
+template <typename T> __device__ inline T wsumT(T v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// Sum of three doubles over the workgroup, broadcast to all threads.
-__device__ inline void block_sum3(double &a, double &b, double &c, double *lds) {
-  a = wsum(a); b = wsum(b); c = wsum(c);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  __syncthreads();
-  if (lane == 0) { lds[3 * wave] = a; lds[3 * wave + 1] = b; lds[3 * wave + 2] = c; }
-  __syncthreads();
-  a = b = c = 0;
-  for (int w = 0; w < nw; ++w) { a += lds[3 * w]; b += lds[3 * w + 1]; c += lds[3 * w + 2]; }
 }
 
 template <typename T>
@@ -38,7 +27,7 @@ __global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__res
                                                     int nrhs) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);          // [12][bvol]
-  __shared__ double red[3 * 16];
+  __shared__ T red[4][3];                        // per-wave partial sums (<= 4 waves)
   // one workgroup per (block, rhs); the right-hand sides of one block are
   // consecutive tiles of one XCD, so its links are read from HBM once and
   // then come from that XCD's L2
@@ -88,26 +77,38 @@ __global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__res
     for (int i = 0; i < 12; ++i) { rho[i] = mk<T>(0, 0); e[i] = mk<T>(0, 0); }
   }
 
-  for (int it = 0; it < n_mr; ++it) {
-    __syncthreads();
-    if (active)
+  // MR steps on the block: rho lives in LDS so that block neighbours see it.
+  // Two barriers per step: after the partial sums (all reads of the old rho
+  // are done), and after the new rho is stored.  Sums are in T (FP32 for the
+  // FP32 smoother).
+  const int lane = t & 63, wave = t >> 6, nwv = blockDim.x >> 6;
+  // bit mu: the forward / backward neighbour in direction mu lies in the block
+  // (register bit tests instead of runtime indexing of the coordinate array)
+  int fmask = 0, bmask = 0;
 #pragma unroll
-      for (int i = 0; i < 12; ++i) lds[i * g.bvol + t] = rho[i];
-    __syncthreads();
-    double num_re = 0, num_im = 0, den = 0;
+  for (int mu = 0; mu < 4; ++mu) {
+    fmask |= (c.l[mu] + 1 < g.b[mu]) ? (1 << mu) : 0;
+    bmask |= (c.l[mu] > 0) ? (1 << mu) : 0;
+  }
+  if (active)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) lds[i * g.bvol + t] = rho[i];
+  __syncthreads();
+  for (int it = 0; it < n_mr; ++it) {
+    T num_re = 0, num_im = 0, den = 0;
     if (active) {
       cplx<T> acc[12];
 #pragma unroll
       for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
 #pragma unroll 1
       for (int mu = 0; mu < 4; ++mu) {
-        if (c.l[mu] + 1 < g.b[mu]) {
+        if ((fmask >> mu) & 1) {
           const int tn = t + g.sl[mu];
 #pragma unroll
           for (int i = 0; i < 12; ++i) q[i] = lds[i * g.bvol + tn];
           hop(mu, true, q, U, g.V, s, (T)1, acc);
         }
-        if (c.l[mu] > 0) {
+        if ((bmask >> mu) & 1) {
           const int tn = t - g.sl[mu];
 #pragma unroll
           for (int i = 0; i < 12; ++i) q[i] = lds[i * g.bvol + tn];
@@ -119,27 +120,31 @@ __global__ void __launch_bounds__(256) k_sap_colour(Geom g, const cplx<T> *__res
         const T g5 = (i < 6) ? (T)1 : (T)-1;
         p[i] = diag * rho[i] - (T)0.5 * acc[i] - (sgm * g5) * rho[i];
         // <p, rho> and <p, p>
-        num_re += (double)p[i].re * rho[i].re + (double)p[i].im * rho[i].im;
-        num_im += (double)p[i].re * rho[i].im - (double)p[i].im * rho[i].re;
-        den += (double)p[i].re * p[i].re + (double)p[i].im * p[i].im;
+        num_re += p[i].re * rho[i].re + p[i].im * rho[i].im;
+        num_im += p[i].re * rho[i].im - p[i].im * rho[i].re;
+        den += p[i].re * p[i].re + p[i].im * p[i].im;
       }
     }
-    block_sum3(num_re, num_im, den, red);
+    num_re = wsumT(num_re); num_im = wsumT(num_im); den = wsumT(den);
+    if (lane == 0) { red[wave][0] = num_re; red[wave][1] = num_im; red[wave][2] = den; }
+    __syncthreads();
+    num_re = num_im = den = 0;
+    for (int w = 0; w < nwv; ++w) { num_re += red[w][0]; num_im += red[w][1]; den += red[w][2]; }
     cplx<T> alpha = mk<T>(0, 0);
-    if (den > 0) alpha = mk<T>((T)(num_re / den), (T)(num_im / den));
+    if (den > 0) alpha = mk<T>(num_re / den, num_im / den);
     if (active)
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
         e[i] = e[i] + alpha * rho[i];
         rho[i] = rho[i] - alpha * p[i];
+        lds[i * g.bvol + t] = rho[i];
       }
+    __syncthreads();
   }
-  __syncthreads();
   if (active)
 #pragma unroll
     for (int i = 0; i < 12; ++i) z[(long long)i * g.V + s] = z[(long long)i * g.V + s] + e[i];
 }
-
 
 }  // namespace
 
