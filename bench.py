@@ -319,6 +319,24 @@ def main():
                      "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
                      "bytes_per_launch": round(k_bytes / max(k_launches, 1))},
     }
+    # the metric's Dirac-apply bandwidth is quoted at 32^3 x 64: measure it there
+    # (after the timed step) when the workload is another lattice
+    if args.workload != "large":
+        big = load_golden(WORKLOADS["large"]["golden"])
+        bdims = tuple(big["dims"])
+        bV = int(np.prod(bdims))
+        bU = torch.from_numpy(lqsynth.gauge_field(bdims, big["eps"], big["field_seed"])).cuda()
+        bctx = Context(bdims, big["t_bc"])
+        bx = device_gaussian(1, bdims, big["field_seed"] + 3, torch)
+        b64 = time_q_apply(bctx, bU, big["m0"], bx, 20, torch)
+        b32 = time_q_apply(bctx, bU.to(torch.complex64), big["m0"], bx.to(torch.complex64), 20, torch)
+        out["config"]["dirac_apply_gbs_32x32x32x64"] = {"fp64": round(960.0 * bV / b64 / 1e9, 1),
+                                                         "fp32": round(480.0 * bV / b32 / 1e9, 1),
+                                                         "fp64_ms": round(b64 * 1e3, 4), "fp32_ms": round(b32 * 1e3, 4)}
+        log(f"q_apply at 32^3x64: FP64 {b64 * 1e3:.3f} ms, FP32 {b32 * 1e3:.3f} ms")
+        del bU, bx, bctx
+    else:
+        out["config"]["dirac_apply_gbs_32x32x32x64"] = out["config"]["dirac_apply_gbs"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle Q apply on the host)")
         x_host = x[0].cpu().numpy()

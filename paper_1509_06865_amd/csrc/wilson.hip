@@ -213,9 +213,10 @@ void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y
   constexpr int R = wilson_group<T>();
   // algorithmic bytes: links once, each field in and out (and b when forming residuals)
   KTimerScope kt(KT_WILSON, (double)g.V * (36.0 + nrhs * (mode == W_RESID ? 36.0 : 24.0)) * sizeof(cplx<T>));
-  if (nrhs == 1 && mode == W_QSHIFT && g.nblk == 1 && sig.s[0] == 0.0 && g.L[3] >= 2) {
-    constexpr int TC = 8;                      // timeslices per thread
-    const long long cols = (long long)g.L[0] * g.L[1] * g.L[2] * ((g.L[3] + TC - 1) / TC);
+  constexpr int TC = 8;                        // timeslices per thread of the column kernel
+  const long long cols = (long long)g.L[0] * g.L[1] * g.L[2] * ((g.L[3] + TC - 1) / TC);
+  // the column kernel when its columns fill the GPU (>= 256 workgroups; 32^3 x 64: 1024)
+  if (nrhs == 1 && mode == W_QSHIFT && g.nblk == 1 && sig.s[0] == 0.0 && g.L[3] >= 2 && cols >= 256 * 256) {
     LQ_LAUNCH(kt, (k_wilson_tcol<T>), dim3(blocks_for(cols, 256)), dim3(256), 0, st, g, U, x, y, (T)m0, TC);
   } else if (nrhs == 1) {
     const dim3 grid(blocks_for(g.V, 256), 1);

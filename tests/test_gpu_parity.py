@@ -81,6 +81,28 @@ def test_q_apply_many_rhs_chunks():
     assert relmax(y, ref) < 1e-13
 
 
+def test_q_apply_timeslice_columns_partial_chunk_antiperiodic():
+    # 32^3 x 12, t antiperiodic, one field: the timeslice-column kernel with a
+    # partial last column (8 + 4 timeslices); sampled sites on both sides of
+    # the column boundary and of the t boundary, against the oracle.
+    from oracle.dirac import apply_Q_sites
+    dims = (32, 32, 32, 12)
+    U = lqsynth.gauge_field(dims, 0.25, 61)
+    lat = Lattice(dims, -1)
+    x = lqsynth.gaussian_spinors(1, dims, 62)
+    c = _ctx(dims, -1)
+    Ud = dev(U)
+    y64 = host(c.q_apply(Ud, -0.1, dev(x))[0])
+    y32 = host(c.q_apply(Ud.to(torch.complex64), -0.1, dev(x, torch.complex64))[0])
+    S3 = 32 ** 3
+    rng = np.random.default_rng(63)
+    sp = rng.integers(0, S3, 12)
+    sites = np.concatenate([sp + S3 * t for t in (0, 7, 8, 11)] + [[0, S3 - 1, 12 * S3 - 1]])
+    ref = apply_Q_sites(U, -0.1, x[0], lat, sites)
+    assert relmax(y64[:, sites], ref) < 1e-13
+    assert relmax(y32[:, sites], ref) < 2e-6
+
+
 def test_q_apply_full_size_sampled_sites():
     # 32^3 x 64, the benchmark lattice: sampled output sites against the
     # oracle's site-by-site evaluation of the definition.
