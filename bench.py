@@ -210,6 +210,7 @@ def main():
     # converge within one run's time budget yet (its interior shifts defeat the two-level solver)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true", help="skip the all-FP64 comparison solve")
     ap.add_argument("--n-eig", type=int, default=None, help="override the workload's eigenpair count")
     ap.add_argument("--guard", type=int, default=None)
     ap.add_argument("--nv", type=int, default=None)
@@ -319,6 +320,25 @@ def main():
                      "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
                      "bytes_per_launch": round(k_bytes / max(k_launches, 1))},
     }
+    # the same solve on the all-FP64 GPU path (smoother and coarse solves in FP64
+    # too), after the timed steps: time and agreement of the eigenvalues
+    if not args.no_fp64_compare and args.workload != "large":
+        prm64 = MGParams(precision=0, rqi_guard=wl["guard"], rayleigh_ritz=1, rqi_max_sweeps=args.max_sweeps,
+                         **wl["params"])
+        torch.cuda.synchronize()
+        a = time.time()
+        ctx.mg_setup(U, m0, wl["agg"], tv0, prm64)
+        lam64, _, res64, info64 = ctx.rqi_lowmodes(wl["n_eig"], wl["tol"], V0=V0)
+        torch.cuda.synchronize()
+        t64p = time.time() - a
+        lam_m, lam_d = np.array(lam), np.array(lam64)
+        out["config"]["fp64_path"] = {"s": round(t64p, 3), "converged": info64["converged"],
+                                      "sweeps": info64["sweeps"], "fgmres_iters": info64["fgmres_iters"],
+                                      "max_residual": float(max(res64)),
+                                      "max_rel_lambda_diff_vs_mixed": float(np.abs(lam_m - lam_d).max()
+                                                                            / np.abs(lam_d).max())}
+        log(f"all-FP64 path: {t64p:.2f} s, converged {info64['converged']}, sweeps {info64['sweeps']}, "
+            f"max |dlambda|/|lambda| vs mixed {out['config']['fp64_path']['max_rel_lambda_diff_vs_mixed']:.2e}")
     # the metric's Dirac-apply bandwidth is quoted at 32^3 x 64: measure it there
     # (after the timed step) when the workload is another lattice
     if args.workload != "large":
