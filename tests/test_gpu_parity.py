@@ -345,8 +345,9 @@ def test_rqi_benchmark_workload_returns_exact_pairs():
     from paper_1509_06865_amd import MGParams
     c = _ctx(dims, bc)
     c.mg_setup(dev(U), m0, (4, 4, 4, 4), dev(lqsynth.gaussian_spinors(20, dims, 202)),
-               MGParams(precision=1, rqi_block=16, fgmres_m=10, n_setup=4, coarse_m=40, coarse_restarts=1,
-                        coarse_tol=0.3, rqi_start_passes=6, rqi_guard=70, rayleigh_ritz=1, rqi_max_sweeps=20))
+               MGParams(precision=1, rqi_block=16, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
+                        coarse_tol=0.3, rqi_start_passes=6, rqi_solve_restarts=0, rqi_guard=70, rayleigh_ritz=1,
+                        rqi_max_sweeps=20))
     V0 = dev(lqsynth.gaussian_spinors(50 + 70 - 20, dims, 203))
     lam, V, res, info = c.rqi_lowmodes(50, 1e-10, V0=V0)
     assert info["converged"], info
