@@ -136,7 +136,8 @@ def cpu_baseline(U_host, m0, dims, t_bc, x_host, n_outer):
 # kernel classes of the library's timer (paper_1509_06865_amd.KT_*) and how
 # their algorithmic bytes are counted
 KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
-          "sap": (1, "SAP colour pass k_sap_colour (links once + r, z in, z out per field)"),
+          "sap": (1, "SAP colour pass k_sap_colour (the colour's links once + per field r, z on all sites "
+                     "(own and halo), z out)"),
           "restrict": (2, "restriction k_restrict (P once + fields + coarse out)"),
           "prolong": (3, "prolongation k_prolong"),
           "coarse": (4, "coarse operator apply k_coarse_apply (< 1024 coarse sites) / k_coarse_apply_multi "

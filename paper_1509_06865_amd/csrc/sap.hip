@@ -153,8 +153,9 @@ void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T
                        int nblocks, double m0, const Shifts &sig, int nrhs, int n_mr, hipStream_t st) {
   if (nblocks <= 0 || nrhs <= 0) return;
   const int threads = ((g.bvol + 63) / 64) * 64;
-  // algorithmic bytes: the colour's links once; per field r, z in and z out
-  KTimerScope kt(KT_SAP, (double)nblocks * g.bvol * (36.0 + 36.0 * nrhs) * sizeof(cplx<T>));
+  // algorithmic bytes: the colour's links once; per field r, z of the colour's
+  // sites and of the other colour's (the blocks' halo), z out
+  KTimerScope kt(KT_SAP, (double)nblocks * g.bvol * (36.0 + 48.0 * nrhs) * sizeof(cplx<T>));
   const size_t lds = (size_t)12 * g.bvol * sizeof(cplx<T>);
   LQ_LAUNCH(kt, (k_sap_colour<T>), dim3(nblocks * nrhs), dim3(threads), lds, st, g, U, r, z, blocks, (T)m0,
                      sig, n_mr, nrhs);
