@@ -228,9 +228,10 @@ void combine(lq_ctx *c, int nb, const c128 *E, long long estride, int nw, const 
 template <typename T>
 std::vector<double> norms(lq_ctx *c, const cplx<T> *w, long long n, int nrhs) {
   std::vector<double> r(nrhs);
-  for (int k = 0; k < nrhs; ++k) {
-    auto d = dots<T>(c, 1, w + k * n, 0, 0, w + k * n, 0, n, 1);
-    r[k] = std::sqrt(std::max(0.0, d[0].real()));
+  for (int k0 = 0; k0 < nrhs; k0 += kMaxRhs) {           // one launch per 16 vectors
+    const int nk = std::min(kMaxRhs, nrhs - k0);
+    auto d = dots<T>(c, 1, w + k0 * n, 0, n, w + k0 * n, n, n, nk);
+    for (int k = 0; k < nk; ++k) r[k0 + k] = std::sqrt(std::max(0.0, d[k].real()));
   }
   return r;
 }
@@ -521,52 +522,115 @@ bool solve_shifted(lq_ctx *c, int nrhs, const double *sig, const c128 *b, c128 *
                                1);
 }
 
-// Eigen-decomposition of a Hermitian n x n matrix (row-major) by cyclic
-// Jacobi rotations: on return A is diagonal (the eigenvalues) and the columns
-// of Vm are the eigenvectors.  Each step first rotates the phase of column q
-// so that A[p][q] is real, then applies the real symmetric Jacobi rotation.
-void jacobi_eigh(int n, std::vector<cd> &A, std::vector<cd> &Vm) {
-  Vm.assign((size_t)n * n, cd(0));
-  for (int i = 0; i < n; ++i) Vm[(size_t)i * n + i] = 1.0;
+// Hermitian eigensolver: Householder reduction to tridiagonal form, a diagonal
+// phase change that makes the tridiagonal real, and the implicit QL iteration
+// with Wilkinson shifts.  On return A = diag(eigenvalues) (real parts on the
+// diagonal) and Vm holds the orthonormal eigenvectors as columns (row-major).
+void herm_eigh(int n, std::vector<cd> &A, std::vector<cd> &Vm) {
   auto a = [&](int i, int j) -> cd & { return A[(size_t)i * n + j]; };
-  auto v = [&](int i, int j) -> cd & { return Vm[(size_t)i * n + j]; };
-  double scale = 0;
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) scale += std::norm(a(i, j));
-  scale = std::sqrt(scale);
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = i + 1; j < n; ++j) off += std::norm(a(i, j));
-    if (std::sqrt(off) <= 1e-16 * scale) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double r = std::abs(a(p, q));
-        if (r <= 1e-300) continue;
-        const cd ph = std::conj(a(p, q)) / r;          // column q times ph, row q times conj(ph)
-        for (int k = 0; k < n; ++k) { a(k, q) *= ph; v(k, q) *= ph; }
-        for (int k = 0; k < n; ++k) a(q, k) *= std::conj(ph);
-        const double apq = a(p, q).real();
-        const double tau = (a(q, q).real() - a(p, p).real()) / (2.0 * apq);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-        const double cth = 1.0 / std::sqrt(1.0 + t * t), sth = t * cth;
-        for (int k = 0; k < n; ++k) {
-          const cd kp = a(k, p), kq = a(k, q);
-          a(k, p) = cth * kp - sth * kq;
-          a(k, q) = sth * kp + cth * kq;
-          const cd vp = v(k, p), vq = v(k, q);
-          v(k, p) = cth * vp - sth * vq;
-          v(k, q) = sth * vp + cth * vq;
-        }
-        for (int k = 0; k < n; ++k) {
-          const cd pk = a(p, k), qk = a(q, k);
-          a(p, k) = cth * pk - sth * qk;
-          a(q, k) = sth * pk + cth * qk;
-        }
-        a(p, q) = 0;
-        a(q, p) = 0;
+  Vm.assign((size_t)n * n, cd(0));
+  auto q = [&](int i, int j) -> cd & { return Vm[(size_t)i * n + j]; };
+  for (int i = 0; i < n; ++i) q(i, i) = 1.0;
+  std::vector<cd> v(n), p(n), w(n);
+  // 1. A <- H A H with H = 1 - 2 v v^dag zeroing column k below the subdiagonal
+  for (int k = 0; k + 2 < n; ++k) {
+    double xn = 0;
+    for (int i = k + 1; i < n; ++i) xn += std::norm(a(i, k));
+    xn = std::sqrt(xn);
+    if (xn == 0) continue;
+    const cd x0 = a(k + 1, k);
+    const cd ph = (std::abs(x0) > 0) ? x0 / std::abs(x0) : cd(1.0);
+    const cd alpha = -ph * xn;
+    double vn = 0;
+    for (int i = k + 1; i < n; ++i) {
+      v[i] = a(i, k) - (i == k + 1 ? alpha : cd(0));
+      vn += std::norm(v[i]);
+    }
+    vn = std::sqrt(vn);
+    if (vn == 0) continue;
+    for (int i = k + 1; i < n; ++i) v[i] /= vn;
+    // full rows/cols k..n-1 take part: p = A v over the trailing block (column k included)
+    for (int i = k; i < n; ++i) {
+      cd s = 0;
+      for (int j = k + 1; j < n; ++j) s += a(i, j) * v[j];
+      p[i] = s;
+    }
+    double K = 0;
+    for (int i = k + 1; i < n; ++i) K += (std::conj(v[i]) * p[i]).real();
+    // w = p - K v (v zero at index k)
+    for (int i = k; i < n; ++i) w[i] = p[i] - (i > k ? K * v[i] : cd(0));
+    // A <- A - 2 (v w^dag + w v^dag) on rows/cols k..n-1
+    for (int i = k; i < n; ++i) {
+      const cd vi = (i > k) ? v[i] : cd(0), wi = w[i];
+      for (int j = k; j < n; ++j) {
+        const cd vj = (j > k) ? v[j] : cd(0);
+        a(i, j) -= 2.0 * (vi * std::conj(w[j]) + wi * std::conj(vj));
       }
+    }
+    // Q <- Q H
+    for (int i = 0; i < n; ++i) {
+      cd s = 0;
+      for (int j = k + 1; j < n; ++j) s += q(i, j) * v[j];
+      for (int j = k + 1; j < n; ++j) q(i, j) -= 2.0 * s * std::conj(v[j]);
+    }
   }
+  // 2. real tridiagonal: d_i = A_ii, e_i = |A_{i+1,i}|; phases into Q's columns
+  std::vector<double> d(n), e(n, 0.0);
+  cd phi = 1.0;
+  for (int i = 0; i < n; ++i) {
+    d[i] = a(i, i).real();
+    if (i > 0) {
+      const cd sub = a(i, i - 1);
+      const double r = std::abs(sub);
+      if (r > 0) phi *= sub / r;
+      for (int k = 0; k < n; ++k) q(k, i) *= phi;
+      e[i - 1] = r;
+    }
+  }
+  // 3. implicit QL with Wilkinson shifts; rotations applied to Q's columns
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 1e-16 * dd) break;
+      }
+      if (m == l) break;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1, c = 1, pp = 0;
+      int i = m - 1;
+      for (; i >= l; --i) {
+        double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0) {
+          d[i + 1] -= pp;
+          e[m] = 0;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        for (int k = 0; k < n; ++k) {
+          const cd t = q(k, i + 1);
+          q(k, i + 1) = s * q(k, i) + c * t;
+          q(k, i) = c * q(k, i) - s * t;
+        }
+      }
+      if (r == 0 && i >= l) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0;
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) a(i, j) = (i == j) ? cd(d[i]) : cd(0);
 }
 
 // Rayleigh-Ritz on span(E) (E orthonormal, n fields): H = E^dag Q E, H = C w C^dag,
@@ -661,7 +725,7 @@ void rayleigh_ritz_tail(lq_ctx *c, c128 *E, int n, int L, std::vector<double> &l
       Tt[(size_t)j * m + i] = std::conj(h);
     }
   std::vector<cd> Zm;
-  jacobi_eigh(m, Tt, Zm);
+  herm_eigh(m, Tt, Zm);
   // Y = Lc^-dag Z: back substitution with Lc^dag (upper)
   std::vector<cd> Y = Zm;
   for (int col = 0; col < m; ++col)
@@ -710,7 +774,7 @@ void rayleigh_ritz(lq_ctx *c, const c128 *E, int n, std::vector<double> &lam, co
       H[(size_t)j * n + i] = std::conj(h);
     }
   std::vector<cd> Cm;
-  jacobi_eigh(n, H, Cm);
+  herm_eigh(n, H, Cm);
   std::vector<int> o(n);
   for (int i = 0; i < n; ++i) o[i] = i;
   std::sort(o.begin(), o.end(), [&](int a, int b) {
@@ -1171,13 +1235,16 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         for (int q = 0; q < nk; ++q) copy<double>(c, B + q * V12, E + ids[q0 + q] * V12, V12);
         Shifts z = shifts_of(nullptr, 0);
         launch_wilson<double>(c->g, c->U64.p, B, X, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+        // all nk pairs at once: lambda_q = <v_q, Q v_q>, X_q <- Q v_q - lambda_q v_q, eps_q = |X_q|
+        auto d = dots<double>(c, 1, B, 0, V12, X, V12, V12, nk);
+        std::vector<cd> lq(nk);
         for (int q = 0; q < nk; ++q) {
-          const int i = ids[q0 + q];
-          auto d = dots<double>(c, 1, B + q * V12, 0, 0, X + q * V12, 0, V12, 1);
-          lam[i] = d[0].real();
-          axpys<double>(c, 1, B + q * V12, 0, 0, std::vector<cd>{cd(lam[i])}, X + q * V12, 0, V12, 1, -1.0);
-          eps[i] = norms<double>(c, X + q * V12, V12, 1)[0];
+          lam[ids[q0 + q]] = d[q].real();
+          lq[q] = cd(d[q].real());
         }
+        axpys<double>(c, 1, B, 0, V12, lq, X, V12, V12, nk, -1.0);
+        auto nr = norms<double>(c, X, V12, nk);
+        for (int q = 0; q < nk; ++q) eps[ids[q0 + q]] = nr[q];
       }
     };
     // Rayleigh-Ritz on E[L..nw) (orthonormal, orthogonal to E[0..L)), then
