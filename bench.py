@@ -62,9 +62,9 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     # guard bands reach past the near-degenerate momentum shell that the
     # n_eig-th mode lies in (16^4: 12 + 96 modes; 32^3x64: 12 + 24 + 96)
-    "large": dict(golden="large", agg=(4, 4, 4, 4), nv=24, n_eig=100, tol=1e-10, guard=32,
+    "large": dict(golden="large", agg=(4, 4, 4, 4), nv=32, n_eig=100, tol=1e-10, guard=32,
                   params=dict(rqi_block=8, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
-                              coarse_tol=0.15, rqi_start_passes=6)),
+                              coarse_tol=0.15, rqi_start_passes=6, rqi_solve_restarts=0)),
     "medium": dict(golden="medium", agg=(4, 4, 4, 4), nv=20, n_eig=50, tol=1e-10, guard=70,
                    params=dict(rqi_block=16, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
                                coarse_tol=0.3, rqi_start_passes=6, rqi_solve_restarts=0)),

@@ -167,6 +167,15 @@ int rqi_lowmodes(lq_ctx *ctx, int n_eig, double tol, double *lambda,
 int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
                       long long n, lq_c128 *out);
 
+/* ---- dense helper ----------------------------------------------------------- */
+/* Eigen-decomposition of the Hermitian part of the n x n matrix A (host,
+ * row-major): w[j] ascending, V (host, row-major) holds the orthonormal
+ * eigenvectors as columns, A V = V diag(w).  The Rayleigh-Ritz step of the
+ * eigensolver (the projected problem V^dag Q V of Alg. 1's iterates) uses this
+ * routine (Householder tridiagonalisation, implicit QL).  No context, no
+ * device.  Errors: LQ_ERR_ARG. */
+int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V);
+
 /* ---- kernel timing (measurement of the hot kernels against the roofline) -- */
 /* Kernel classes: 0 Wilson stencil (q_apply and the solves), 1 SAP colour
  * passes, 2 restriction, 3 prolongation, 4 coarse operator apply, 5 Gram

@@ -29,46 +29,20 @@ __device__ inline double block_sum(double v, double *lds) {
   return r;
 }
 
-// The last workgroup to finish (counted with an atomic after a fence) adds
-// the chunk partials of every (i, k) in chunk order, writes out[i][k] and
-// re-arms the counter: one launch, and the same order of additions every time.
-__device__ inline void finish_dots(int nv, int nrhs, int nchunks, const c128 *partial, c128 *out,
-                                   unsigned *counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned total = gridDim.x * gridDim.y * gridDim.z;
-    last = (atomicAdd(counter, 1u) == total - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int ik = threadIdx.x; ik < nv * nrhs; ik += blockDim.x) {
-    double re = 0, im = 0;
-    const volatile c128 *p = partial + (long long)ik * nchunks;
-    for (int c = 0; c < nchunks; ++c) { re += p[c].re; im += p[c].im; }
-    out[ik] = c128{re, im};
-  }
-  if (threadIdx.x == 0) *counter = 0u;
-}
-
-// Stage 1: partial[g*kDotGroup + i][k][chunk]; with out != nullptr the last
-// workgroup also performs the final reduction.
+// Stage 1: partial[g*kDotGroup + i][k][chunk].  Rows past nv read row nv - 1
+// and are dropped, so the loads carry no branches and stay in flight together.
 template <typename T>
 __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx<T> *__restrict__ vbase,
                                                               long long vstride, long long rstride,
                                                               const cplx<T> *__restrict__ w, long long wstride,
                                                               long long n, c128 *__restrict__ partial,
-                                                              const int *__restrict__ active, c128 *out,
-                                                              unsigned *counter) {
+                                                              const int *__restrict__ active) {
   __shared__ double lds[kDotThreads / 64];
   const int chunk = blockIdx.x, k = blockIdx.y, grp = blockIdx.z;
   const int nchunks = gridDim.x, nrhs = gridDim.y;
   if (active && !active[k]) {
     if (threadIdx.x < kDotGroup && grp * kDotGroup + (int)threadIdx.x < nv)
       partial[((long long)(grp * kDotGroup + threadIdx.x) * nrhs + k) * nchunks + chunk] = c128{0, 0};
-    if (out != nullptr) finish_dots(nv, nrhs, nchunks, partial, out, counter);
     return;
   }
   const long long per = (n + nchunks - 1) / nchunks;
@@ -78,15 +52,16 @@ __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx
 #pragma unroll
   for (int i = 0; i < kDotGroup; ++i) { re[i] = 0; im[i] = 0; }
   const int i0 = grp * kDotGroup;
+  const cplx<T> *vk[kDotGroup];
+#pragma unroll
+  for (int i = 0; i < kDotGroup; ++i) vk[i] = vbase + (long long)(i0 + i < nv ? i0 + i : nv - 1) * vstride + k * rstride;
   for (long long e = lo + threadIdx.x; e < hi; e += kDotThreads) {
     const cplx<T> wv = wk[e];
 #pragma unroll
     for (int i = 0; i < kDotGroup; ++i) {
-      if (i0 + i < nv) {
-        const cplx<T> v = vbase[(i0 + i) * vstride + k * rstride + e];
-        re[i] += (double)v.re * wv.re + (double)v.im * wv.im;
-        im[i] += (double)v.re * wv.im - (double)v.im * wv.re;
-      }
+      const cplx<T> v = vk[i][e];
+      re[i] += (double)v.re * wv.re + (double)v.im * wv.im;
+      im[i] += (double)v.re * wv.im - (double)v.im * wv.re;
     }
   }
 #pragma unroll
@@ -96,7 +71,6 @@ __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx
     double si = block_sum(im[i], lds);
     if (threadIdx.x == 0) partial[((long long)(i0 + i) * nrhs + k) * nchunks + chunk] = c128{sr, si};
   }
-  if (out != nullptr) finish_dots(nv, nrhs, nchunks, partial, out, counter);
 }
 
 // Stage 2: one wave per (i, k) sums the chunk partials in a fixed tree.
@@ -120,6 +94,7 @@ __global__ void k_multi_axpy(int nv, const cplx<T> *__restrict__ vbase, long lon
   const int k = blockIdx.y;
   if (e >= n || (active && !active[k])) return;
   cplx<T> acc = w[k * wstride + e];
+#pragma unroll 4
   for (int i = 0; i < nv; ++i) {
     const c128 hh = h[i * nrhs + k];
     const cplx<T> c = {(T)(sign * hh.re), (T)(sign * hh.im)};
@@ -277,7 +252,7 @@ void launch_arnoldi_solve(int m, int nrhs, const c128 *H, const c128 *g, const i
 
 size_t dots_scratch_elems(int nv, int nrhs) {
   const int groups = (nv + kDotGroup - 1) / kDotGroup;
-  return (size_t)groups * kDotGroup * nrhs * kDotChunks + 1;     // + counter slot
+  return (size_t)groups * kDotGroup * nrhs * kDotChunks;
 }
 
 template <typename T>
@@ -289,21 +264,12 @@ void launch_dots(int nv, const cplx<T> *vbase, long long vstride, long long rstr
   if (nchunks > kDotChunks) nchunks = kDotChunks;
   if (nchunks < 1) nchunks = 1;
   const int groups = (nv + kDotGroup - 1) / kDotGroup;
-  // scratch[0] holds the completion counter (zero when the scratch is
-  // allocated, re-armed by every fused launch); the partial sums follow it
-  unsigned *counter = reinterpret_cast<unsigned *>(scratch);
-  c128 *partial = scratch + 1;
-  // The one-launch form (final sum by the last workgroup) serialises that sum
-  // on uncached loads and measured slower than the second launch, which
-  // reduces every (i, k) with its own wave; it stays available but is off.
-  const bool fused = false;
+  c128 *partial = scratch;
   hipLaunchKernelGGL((k_dots_partial<T>), dim3(nchunks, nrhs, groups), dim3(kDotThreads), 0, st, nv, vbase,
-                     vstride, rstride, w, wstride, n, partial, active, fused ? out : nullptr, counter);
+                     vstride, rstride, w, wstride, n, partial, active);
   LQ_HIP(hipGetLastError());
-  if (!fused) {
-    hipLaunchKernelGGL(k_dots_final, dim3(nv * nrhs), dim3(64), 0, st, partial, nchunks, out);
-    LQ_HIP(hipGetLastError());
-  }
+  hipLaunchKernelGGL(k_dots_final, dim3(nv * nrhs), dim3(64), 0, st, partial, nchunks, out);
+  LQ_HIP(hipGetLastError());
 }
 
 template <typename T>

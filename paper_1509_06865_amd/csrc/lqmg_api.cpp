@@ -635,7 +635,6 @@ void herm_eigh(int n, std::vector<cd> &A, std::vector<cd> &Vm) {
 
 // Rayleigh-Ritz on span(E) (E orthonormal, n fields): H = E^dag Q E, H = C w C^dag,
 // E <- E C ordered by (|w|, w); lam receives w.
-void rayleigh_ritz(lq_ctx *c, const c128 *E, int n, std::vector<double> &lam, const std::vector<c128 *> &dst);
 
 // Reorder the n fields of E in place so that slot p receives old slot order[p]
 // (cycle following with one spare field).
@@ -755,47 +754,6 @@ void rayleigh_ritz_tail(lq_ctx *c, c128 *E, int n, int L, std::vector<double> &l
   sync(c);
 }
 
-void rayleigh_ritz(lq_ctx *c, const c128 *E, int n, std::vector<double> &lam, const std::vector<c128 *> &dst) {
-  const long long V12 = 12LL * c->g.V;
-  c128 *QE = c->tmpA.get((size_t)kMaxRhs * V12);
-  std::vector<cd> H((size_t)n * n);
-  Shifts z = shifts_of(nullptr, 0);
-  for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
-    const int nk = std::min(kMaxRhs, n - j0);
-    launch_wilson<double>(c->g, c->U64.p, E + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
-    auto d = gram(c, n, E, V12, nk, QE, V12, V12);                // d[i][k] = <E_i, Q E_{j0+k}>
-    for (int i = 0; i < n; ++i)
-      for (int k = 0; k < nk; ++k) H[(size_t)i * n + j0 + k] = d[(size_t)i * nk + k];
-  }
-  for (int i = 0; i < n; ++i)
-    for (int j = i; j < n; ++j) {
-      const cd h = 0.5 * (H[(size_t)i * n + j] + std::conj(H[(size_t)j * n + i]));
-      H[(size_t)i * n + j] = h;
-      H[(size_t)j * n + i] = std::conj(h);
-    }
-  std::vector<cd> Cm;
-  herm_eigh(n, H, Cm);
-  std::vector<int> o(n);
-  for (int i = 0; i < n; ++i) o[i] = i;
-  std::sort(o.begin(), o.end(), [&](int a, int b) {
-    const double wa = H[(size_t)a * n + a].real(), wb = H[(size_t)b * n + b].real();
-    if (std::fabs(wa) != std::fabs(wb)) return std::fabs(wa) < std::fabs(wb);
-    return wa < wb;
-  });
-  // Ritz vector j = sum_i C[i][o_j] E_i, 16 at a time into a work buffer, then
-  // to its destination (which must not overlap E)
-  c128 *NE = c->tmpB.get((size_t)kMaxRhs * V12);
-  for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
-    const int nk = std::min(kMaxRhs, n - j0);
-    std::vector<cd> h((size_t)n * nk);
-    for (int i = 0; i < n; ++i)
-      for (int k = 0; k < nk; ++k) h[(size_t)i * nk + k] = Cm[(size_t)i * n + o[j0 + k]];
-    combine(c, n, E, V12, nk, h, 1.0, NE, V12, V12, false);
-    for (int k = 0; k < nk; ++k) copy<double>(c, dst[j0 + k], NE + k * V12, V12);
-  }
-  for (int j = 0; j < n; ++j) lam[j] = H[(size_t)o[j] * n + o[j]].real();
-  sync(c);
-}
 
 // ---------------------------------------------------------------------------
 // Galerkin correction on the span of the current eigenvector approximations.
@@ -1178,7 +1136,9 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
       copy<double>(c, E, c->W.p, (size_t)n_tv_used * V12);
       if (n_v0 > 0) launch_permute<double>(c->g, (const c128 *)V0, E + n_tv_used * V12, n_v0, true, c->st);
     }
-    orthonormalise(c, E, nw);
+    // with start passes and Rayleigh-Ritz the first generalised Rayleigh-Ritz
+    // step orthonormalises the set; otherwise Alg. 1 starts from orthonormal vectors
+    if (!(c->p.rqi_start_passes > 0 && c->p.rayleigh_ritz)) orthonormalise(c, E, nw);
     std::vector<double> lam(nw, 0.0), eps(nw, 1.0);
     c128 *SEL = c->sel.get((size_t)Nv * V12);
     // P from the current approximations (Alg. 1: "update v_i in P").  With
@@ -1446,6 +1406,35 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     if (stats) *stats = S;
     return done ? LQ_OK : LQ_WARN_NOCONV;
   });
+}
+
+int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V) {
+  if (n < 1 || !A || !w || !V) return LQ_ERR_ARG;
+  try {
+    std::vector<cd> M((size_t)n * n), Z;
+    std::memcpy(M.data(), A, M.size() * sizeof(cd));
+    for (int i = 0; i < n; ++i)                       // use the Hermitian part
+      for (int j = i; j < n; ++j) {
+        const cd h = 0.5 * (M[(size_t)i * n + j] + std::conj(M[(size_t)j * n + i]));
+        M[(size_t)i * n + j] = h;
+        M[(size_t)j * n + i] = std::conj(h);
+      }
+    herm_eigh(n, M, Z);
+    std::vector<int> o(n);
+    for (int i = 0; i < n; ++i) o[i] = i;
+    std::stable_sort(o.begin(), o.end(),
+                     [&](int a, int b) { return M[(size_t)a * n + a].real() < M[(size_t)b * n + b].real(); });
+    for (int j = 0; j < n; ++j) {
+      w[j] = M[(size_t)o[j] * n + o[j]].real();
+      for (int i = 0; i < n; ++i) {
+        const cd z = Z[(size_t)i * n + o[j]];
+        V[(size_t)i * n + j] = lq_c128{z.real(), z.imag()};
+      }
+    }
+  } catch (...) {
+    return LQ_ERR_NUMERIC;
+  }
+  return LQ_OK;
 }
 
 int lq_inner_products(lq_ctx *c, int nb, const lq_c128 *E, int nw, const lq_c128 *W, long long n, lq_c128 *out) {

@@ -23,7 +23,7 @@ SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
-            "lq_kernel_timer_start", "lq_kernel_timer_read"]
+            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -125,6 +125,7 @@ def load():
         "lq_inner_products": (i, [vp, i, vp, i, vp, C.c_longlong, vp]),
         "lq_kernel_timer_start": (i, [i]),
         "lq_kernel_timer_read": (i, [C.POINTER(C.c_longlong), dp, dp]),
+        "lq_herm_eigh": (i, [i, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -286,3 +287,17 @@ def kernel_timer_read():
     if rc != 0:
         raise LQError(rc, "lq_kernel_timer_read failed")
     return n.value, ms.value, by.value
+
+
+def herm_eigh(A):
+    """Eigenvalues (ascending) and eigenvectors (columns) of a host Hermitian
+    complex matrix through the library's dense helper."""
+    import numpy as np
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    w = np.empty(n)
+    V = np.empty((n, n), dtype=np.complex128)
+    rc = load().lq_herm_eigh(n, C.c_void_p(A.ctypes.data), C.c_void_p(w.ctypes.data), C.c_void_p(V.ctypes.data))
+    if rc != 0:
+        raise LQError(rc, "lq_herm_eigh failed")
+    return w, V

@@ -175,6 +175,33 @@ def test_coarse_apply_galerkin_identity_full_blocks():
         assert relmax(y[k], ref) < 2e-5
 
 
+def test_argument_and_state_errors_are_reported():
+    # bad sizes, calls before mg_setup and impossible aggregations come back as
+    # error codes (raised by the binding), with no kernel launched
+    from paper_1509_06865_amd import LQError, MGParams
+    dims, bc, eps, seed, m0 = tiny("tiny_periodic")
+    c = _ctx(dims, bc)
+    U = dev(lqsynth.gauge_field(dims, eps, seed))
+    x = dev(lqsynth.gaussian_spinors(2, dims, 71))
+    with pytest.raises(LQError):
+        c.mg_solve_shifted([0.0], x[:1], 1e-6)                      # before mg_setup
+    with pytest.raises(LQError):
+        c.mg_setup(U, m0, (3, 2, 2, 2), x, MGParams(n_setup=0))     # 3 does not divide 4
+    with pytest.raises(LQError):
+        c.mg_setup(U, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(33, dims, 72)), MGParams(n_setup=0))
+    with pytest.raises(LQError):
+        c.mg_setup(U, m0, (2, 2, 2, 2), x, MGParams(n_setup=0, rqi_block=17))
+    c.mg_setup(U, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(4, dims, 73)), MGParams(n_setup=0, rqi_guard=2))
+    with pytest.raises(LQError):
+        c.mg_solve_shifted([0.0] * 17, dev(lqsynth.gaussian_spinors(17, dims, 74)), 1e-6)   # > 16 shifts
+    with pytest.raises(LQError):
+        c.rqi_lowmodes(4, 1e-10, V0=dev(lqsynth.gaussian_spinors(5, dims, 75)))             # wrong V0 count
+    # the context stays usable after the errors
+    y = host(c.q_apply(U, m0, x))
+    ref = WilsonOp(lqsynth.gauge_field(dims, eps, seed), m0, Lattice(dims, bc)).Q(host(x))
+    assert relmax(y, ref) < 1e-13
+
+
 def test_kernel_timer_counts_wilson_launches_and_bytes():
     # the roofline instrumentation: every Wilson launch of q_apply is timed
     # and credited with 960 B per site (FP64: links, field in, field out)

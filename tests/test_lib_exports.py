@@ -1,9 +1,11 @@
-"""The C-ABI library loads and exports every function include/lqmg.h declares
-(no compute call: this runs without a GPU)."""
+"""The C-ABI library loads and exports every function include/lqmg.h declares,
+and its host-only dense helper is checked against numpy (no device call: this
+runs without a GPU)."""
 import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -51,3 +53,25 @@ def test_create_rejects_bad_arguments():
     assert lib.lq_create(ctypes.byref(h), bad, -1, None) == -1
     good = (ctypes.c_int * 4)(4, 4, 4, 4)
     assert lib.lq_create(ctypes.byref(h), good, 0, None) == -1
+
+
+@pytest.mark.parametrize("n,kind", [(1, "rand"), (7, "rand"), (64, "degen"), (132, "rand"), (132, "degen")])
+def test_dense_hermitian_eigensolver_matches_numpy(n, kind):
+    # the host eigensolver of the Rayleigh-Ritz step, against numpy's LAPACK,
+    # on random spectra and on exactly degenerate ones (clusters of 4)
+    from paper_1509_06865_amd.lqmg import herm_eigh
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    if kind == "rand":
+        A = (X + X.conj().T) / 2
+    else:
+        Qm, _ = np.linalg.qr(X)
+        lam = np.repeat(rng.standard_normal((n + 3) // 4), 4)[:n]
+        A = (Qm * lam) @ Qm.conj().T
+        A = (A + A.conj().T) / 2
+    w, V = herm_eigh(A)
+    ref = np.linalg.eigvalsh(A)
+    scale = max(np.abs(ref).max(), 1.0)
+    assert np.abs(w - ref).max() <= 1e-13 * scale
+    assert np.abs(A @ V - V * w).max() <= 1e-13 * scale
+    assert np.abs(V.conj().T @ V - np.eye(n)).max() <= 1e-13
