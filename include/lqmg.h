@@ -88,6 +88,11 @@ typedef struct {
                            the sigma = 0 preconditioner, re-orthonormalisation and
                            a Rayleigh-Ritz step; 0 = Alg. 1 from the start vectors
                            as given */
+  int graphs;           /* 1 = the coarse GMRES replays the Arnoldi steps between
+                           two convergence checks (8 steps) as one captured HIP
+                           graph, cached per shape; same kernels and bitwise the
+                           same results as 0 (direct launches, the default).
+                           Off while LQ_KT_COARSE is timed */
 } lq_mg_params;
 
 typedef struct {
@@ -175,6 +180,18 @@ int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c1
  * routine (Householder tridiagonalisation, implicit QL).  No context, no
  * device.  Errors: LQ_ERR_ARG. */
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V);
+
+/* ---- coarse-apply kernel choice --------------------------------------------- */
+/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has four
+ * kernels: 0 one wavefront per (coarse site, rhs); 1, 2, 3 one workgroup per
+ * coarse site with each 2Nv x 2Nv block staged in LDS and applied to 4, 8 or
+ * 16 right-hand sides per pass.  By default each coarse solve times the four
+ * on its first call for a shape (precision, coarse sites, 2Nv, rhs count,
+ * device) and keeps the fastest for the process.  lq_coarse_variant(v) with
+ * v in 0..3 forces kernel v for every shape (tests compare them); v = -1
+ * returns to the tuned choice.  Process-wide, not thread-safe.
+ * Errors: LQ_ERR_ARG for v outside -1..3. */
+int lq_coarse_variant(int v);
 
 /* ---- kernel timing (measurement of the hot kernels against the roofline) -- */
 /* Kernel classes: 0 Wilson stencil (q_apply and the solves), 1 SAP colour

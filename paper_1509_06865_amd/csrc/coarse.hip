@@ -3,6 +3,10 @@
 // Stored blocks per coarse site: the self block and the four forward blocks;
 // the backward coupling from A - mu is the conjugate transpose of the
 // forward block of A - mu, because Q_c is Hermitian.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "lq_kernels.h"
 
 namespace lq {
@@ -20,7 +24,7 @@ __device__ inline int cnbr(const CoarseGeom &cg, int A, int mu, int step) {
 template <typename T>
 __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
                                                      const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
-                                                     Shifts sig, bool g5form) {
+                                                     Shifts sig, const double *__restrict__ dsig, bool g5form) {
   __shared__ cplx<T> xs[9][64];
   const int A = blockIdx.x, k = blockIdx.y, i = threadIdx.x;
   const int n2 = cg.n2;
@@ -44,7 +48,7 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T
     const cplx<T> *M = Qc + ((long long)nb[5 + mu] * 5 + 1 + mu) * bs + i;
     for (int j = 0; j < n2; ++j) acc = acc + cmul_conj(M[(long long)j * n2], xs[5 + mu][j]);
   }
-  acc = acc - (T)sig.s[k] * xs[0][i];
+  acc = acc - (T)(dsig ? dsig[k] : sig.s[k]) * xs[0][i];
   if (g5form && i >= n2 / 2) acc = -acc;
   yout[((long long)k * cg.nA + A) * n2 + i] = acc;
 }
@@ -61,8 +65,8 @@ constexpr int kCoarsePerThread = (kCoarseMaxN2 * kCoarseMaxN2 + 255) / 256;
 template <typename T, int KCH>
 __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
                                                             const cplx<T> *__restrict__ xin,
-                                                            cplx<T> *__restrict__ yout, Shifts sig, bool g5form,
-                                                            int nrhs) {
+                                                            cplx<T> *__restrict__ yout, Shifts sig,
+                                                            const double *__restrict__ dsig, bool g5form, int nrhs) {
   __shared__ cplx<T> blk[kCoarseMaxN2 * (kCoarseMaxN2 + 1)];
   __shared__ cplx<T> xs[KCH][kCoarseMaxN2];
   const int A = blockIdx.x;
@@ -133,7 +137,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
         const int k = ks + a * rhs_slots;
         if (k >= kc) break;
         const long long off = ((long long)(k0 + k) * cg.nA + A) * n2 + i;
-        cplx<T> v = acc[a] - (T)sig.s[k0 + k] * xin[off];
+        cplx<T> v = acc[a] - (T)(dsig ? dsig[k0 + k] : sig.s[k0 + k]) * xin[off];
         if (g5form && i >= n2 / 2) v = -v;
         yout[off] = v;
       }
@@ -149,25 +153,118 @@ __global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T
   y[e] = (i >= cg.n2 / 2) ? -v : v;
 }
 
+__global__ void k_set_shifts(Shifts s, int n, double *dst) {
+  const int k = threadIdx.x;
+  if (k < n) dst[k] = s.s[k];
+}
+
+// Variants of the coarse apply: 0 = one wave per (site, rhs); 1..3 = one
+// workgroup per site with the blocks staged in LDS for 4, 8 or 16 rhs per pass.
+constexpr int kCoarseVariants = 4;
+
+template <typename T>
+void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x,
+                           cplx<T> *y, const Shifts &sig, const double *dsig, int nrhs, bool g5form, hipStream_t st) {
+  switch (v) {
+    case 1:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 4>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form, nrhs);
+      break;
+    case 2:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 8>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form, nrhs);
+      break;
+    case 3:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 16>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form,
+                nrhs);
+      break;
+    default:
+      LQ_LAUNCH(kt, (k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, dsig, g5form);
+  }
+  LQ_HIP(hipGetLastError());
+}
+
+// The tuned variant per (precision, coarse sites, 2 Nv, nrhs, device).
+struct CoarseTuneKey {
+  int tsize, nA, n2, nrhs, dev;
+  bool operator<(const CoarseTuneKey &o) const {
+    return std::tie(tsize, nA, n2, nrhs, dev) < std::tie(o.tsize, o.nA, o.n2, o.nrhs, o.dev);
+  }
+};
+std::mutex g_coarse_mu;
+std::map<CoarseTuneKey, int> g_coarse_choice;
+int g_coarse_force = -1;
+
+CoarseTuneKey coarse_key(const CoarseGeom &cg, int tsize, int nrhs) {
+  int dev = 0;
+  LQ_HIP(hipGetDevice(&dev));
+  return {tsize, cg.nA, cg.n2, nrhs, dev};
+}
+
 }  // namespace
+
+int coarse_force_variant(int v) {
+  if (v < -1 || v >= kCoarseVariants) return -1;
+  std::lock_guard<std::mutex> lk(g_coarse_mu);
+  g_coarse_force = v;
+  return 0;
+}
+
+template <typename T>
+int coarse_variant(const CoarseGeom &cg, int nrhs) {
+  std::lock_guard<std::mutex> lk(g_coarse_mu);
+  if (g_coarse_force >= 0) return g_coarse_force;
+  auto it = g_coarse_choice.find(coarse_key(cg, sizeof(T), nrhs));
+  return it == g_coarse_choice.end() ? -1 : it->second;
+}
+
+// Time every variant on the caller's operands (y is overwritten) and keep the
+// fastest for this shape: one warm-up and three timed launches each, on the
+// stream, outside any graph capture.  A shape already tuned is left alone.
+template <typename T>
+int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, int nrhs,
+                      hipStream_t st) {
+  if (coarse_variant<T>(cg, nrhs) >= 0) return coarse_variant<T>(cg, nrhs);
+  Shifts z{};
+  KTimerScope off(KT_COUNT, 0.0);     // never a selected class: untimed
+  hipEvent_t e0, e1;
+  LQ_HIP(hipEventCreate(&e0));
+  LQ_HIP(hipEventCreate(&e1));
+  int best = 0;
+  float tbest = 1e30f;
+  for (int v = 0; v < kCoarseVariants; ++v) {
+    coarse_launch_variant<T>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
+    LQ_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) coarse_launch_variant<T>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
+    LQ_HIP(hipEventRecord(e1, st));
+    LQ_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    LQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < tbest) { tbest = ms; best = v; }
+  }
+  LQ_HIP(hipEventDestroy(e0));
+  LQ_HIP(hipEventDestroy(e1));
+  std::lock_guard<std::mutex> lk(g_coarse_mu);
+  g_coarse_choice[coarse_key(cg, sizeof(T), nrhs)] = best;
+  return best;
+}
+
+void launch_set_shifts(const Shifts &s, int n, double *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_shifts, dim3(1), dim3(kMaxRhs), 0, st, s, n, dst);
+  LQ_HIP(hipGetLastError());
+}
 
 template <typename T>
 void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig,
-                         int nrhs, bool g5form, hipStream_t st) {
+                         int nrhs, bool g5form, hipStream_t st, const double *dsig) {
   // algorithmic bytes: the 5 stored blocks per site once, x in and y out per field
   KTimerScope kt(KT_COARSE, ((double)cg.nA * 5 * cg.n2 * cg.n2 + 2.0 * nrhs * cg.nA * cg.n2) * sizeof(cplx<T>));
-  // Few coarse sites (< 1024, e.g. 256 at 16^4 with 4^4 aggregates: measured
-  // 0.039 ms against 0.089 ms per launch): one wave per (site, rhs) keeps the
-  // GPU busy; many sites: one workgroup per site, blocks read once for all rhs.
-  if (nrhs >= 4 && cg.n2 <= 64 && cg.nA >= 1024) {
-    // FP32: all 16 rhs per pass; FP64 (twice the LDS per element): 8 per pass
-    constexpr int KCH = sizeof(T) == 4 ? 16 : 8;
-    LQ_LAUNCH(kt, (k_coarse_apply_multi<T, KCH>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, g5form,
-                       nrhs);
-  } else {
-    LQ_LAUNCH(kt, (k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, g5form);
+  int v = coarse_variant<T>(cg, nrhs);
+  if (v < 0) {
+    // untuned shape: few coarse sites (< 1024, e.g. 256 at 16^4 with 4^4
+    // aggregates) keep one wave per (site, rhs); many sites stage each block
+    // once for all rhs
+    v = (nrhs >= 4 && cg.nA >= 1024) ? (sizeof(T) == 4 ? 3 : 2) : 0;
   }
-  LQ_HIP(hipGetLastError());
+  coarse_launch_variant<T>(v, kt, cg, Qc, x, y, sig, dsig, nrhs, g5form, st);
 }
 
 template <typename T>
@@ -178,9 +275,13 @@ void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nr
 }
 
 template void launch_coarse_apply<float>(const CoarseGeom &, const c64 *, const c64 *, c64 *, const Shifts &, int,
-                                         bool, hipStream_t);
+                                         bool, hipStream_t, const double *);
 template void launch_coarse_apply<double>(const CoarseGeom &, const c128 *, const c128 *, c128 *, const Shifts &,
-                                          int, bool, hipStream_t);
+                                          int, bool, hipStream_t, const double *);
+template int tune_coarse_apply<float>(const CoarseGeom &, const c64 *, const c64 *, c64 *, int, hipStream_t);
+template int tune_coarse_apply<double>(const CoarseGeom &, const c128 *, const c128 *, c128 *, int, hipStream_t);
+template int coarse_variant<float>(const CoarseGeom &, int);
+template int coarse_variant<double>(const CoarseGeom &, int);
 template void launch_coarse_g5<float>(const CoarseGeom &, const c64 *, c64 *, int, hipStream_t);
 template void launch_coarse_g5<double>(const CoarseGeom &, const c128 *, c128 *, int, hipStream_t);
 

@@ -105,10 +105,26 @@ struct CoarseGeom {
   int nA;          // coarse sites
   int n2;          // 2 * Nv unknowns per coarse site
 };
-// y_k = g5c^e (Q_c - sigma_k) x_k (e = 1 if gamma5c form); vectors [nrhs][nA][n2]
+// y_k = g5c^e (Q_c - sigma_k) x_k (e = 1 if gamma5c form); vectors [nrhs][nA][n2].
+// sigma_k is read from the device array dsig[k] when dsig is given (a launch
+// whose arguments do not change with the shifts, as graph replay needs), else
+// from sig.  The kernel variant is the one tuned for the shape, if any.
 template <typename T>
 void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y,
-                         const Shifts &sig, int nrhs, bool g5form, hipStream_t st);
+                         const Shifts &sig, int nrhs, bool g5form, hipStream_t st, const double *dsig = nullptr);
+// dst[k] = s.s[k] for k < n, in stream order
+void launch_set_shifts(const Shifts &s, int n, double *dst, hipStream_t st);
+// Time each coarse-apply variant on these operands (y is overwritten), keep the
+// fastest for (precision, nA, n2, nrhs, device) and return it; a tuned shape
+// returns its variant at once.  Synchronises the stream: never under capture.
+template <typename T>
+int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, int nrhs,
+                      hipStream_t st);
+// the variant used for a shape: the forced one, else the tuned one, else -1
+template <typename T>
+int coarse_variant(const CoarseGeom &cg, int nrhs);
+// force variant v (0..3) for every shape, or -1 to use the tuned choice; -1 return = bad v
+int coarse_force_variant(int v);
 // y_k = g5c x_k (elementwise)
 template <typename T>
 void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nrhs, hipStream_t st);

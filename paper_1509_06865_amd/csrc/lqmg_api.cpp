@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -152,12 +153,62 @@ struct lq_ctx {
   DevBuf<c128> sel;                 // vectors that build P [Nv][12][V]
   DevBuf<c128> defl_tmp, defl_u, defl_r;   // Galerkin correction work           // Rayleigh-Ritz: gathered unconverged vectors
   DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
+  DevBuf<double> coarse_sig;        // shifts of the current coarse solve [kMaxRhs]
   int coarse_iters = 0;
+  // captured coarse-GMRES chunks, keyed by shape, step range and every pointer
+  // they use; cap_st is the private stream they are captured on
+  std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+  hipStream_t cap_st = nullptr;
+  ~lq_ctx() {
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+  }
 };
 
 namespace {
 
 void sync(lq_ctx *c) { LQ_HIP(hipStreamSynchronize(c->st)); }
+
+uint64_t key_bits(const void *p) { return (uint64_t)(uintptr_t)p; }
+uint64_t key_bits(double d) {
+  uint64_t u;
+  std::memcpy(&u, &d, sizeof(u));
+  return u;
+}
+
+// The executable graph of `body` (launches on c->st only, no host waits, no
+// memsets), captured on first use of `key` on a private stream and reused.
+// The cache holds at most 256 graphs; when full it is emptied after the
+// stream has drained.
+hipGraphExec_t chunk_graph(lq_ctx *c, const std::vector<uint64_t> &key, const std::function<void()> &body) {
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) return it->second;
+  if (c->graphs.size() >= 256) {
+    sync(c);
+    for (auto &kv : c->graphs) LQ_HIP(hipGraphExecDestroy(kv.second));
+    c->graphs.clear();
+  }
+  if (!c->cap_st) LQ_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  const hipStream_t orig = c->st;
+  LQ_HIP(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeRelaxed));
+  c->st = c->cap_st;
+  hipGraph_t g = nullptr;
+  try {
+    body();
+  } catch (...) {
+    c->st = orig;
+    if (hipStreamEndCapture(c->cap_st, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  c->st = orig;
+  LQ_HIP(hipStreamEndCapture(c->cap_st, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  LQ_HIP(e);
+  c->graphs.emplace(key, ex);
+  return ex;
+}
 
 template <typename T> void zero(lq_ctx *c, cplx<T> *p, size_t n) {
   LQ_HIP(hipMemsetAsync(p, 0, n * sizeof(cplx<T>), c->st));
@@ -250,9 +301,11 @@ template <typename T> struct KOps {
 template <typename T>
 bool gmres_batched(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KOps<T> &ops, const cplx<T> *b,
                    cplx<T> *x, int m, int max_restarts, double tol, int *iters, double *relres,
-                   int check_every) {
+                   int check_every, const std::vector<uint64_t> *graph_id = nullptr) {
   // All Arnoldi bookkeeping stays on the device; the host waits only once per
   // restart cycle, and in between every check_every steps to stop early.
+  // With graph_id (the identity of ops: every pointer and value their launches
+  // use) the steps between two checks are replayed as one captured graph.
   const bool flex = (bool)ops.precond;
   cplx<T> *Vb = kw.V.get((size_t)(m + 1) * nrhs * n);
   cplx<T> *Zb = flex ? kw.Z.get((size_t)m * nrhs * n) : nullptr;
@@ -281,14 +334,8 @@ bool gmres_batched(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KO
     // S.nrm2 holds ||r_k||^2 here
     launch_arnoldi_start(nrhs, m, S.nrm2, S.bn, tol, S.g, S.active, S.kk, S.coef, c->st);
     launch_scale<T>(S.coef, r, n, Vb, n, n, nrhs, false, c->st);
-    for (int j = 0; j < m; ++j) {
-      if (check_every > 0 && j > 0 && j % check_every == 0) {
-        LQ_HIP(hipMemcpyAsync(act.data(), S.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, c->st));
-        sync(c);
-        bool run = false;
-        for (int k = 0; k < nrhs; ++k) run = run || act[k];
-        if (!run) break;
-      }
+    // one Arnoldi step: w = A M v_j orthogonalised (CGS twice), Givens update
+    auto step = [&](int j) {
       cplx<T> *vj = Vb + j * vs, *w = Vb + (j + 1) * vs;
       const cplx<T> *src = vj;
       if (flex) {
@@ -304,6 +351,32 @@ bool gmres_batched(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KO
       launch_arnoldi_update(j, m, nrhs, S.h1, S.h2, S.nrm2, S.H, S.cs, S.sn, S.g, S.bn, tol, S.active, S.kk, S.coef,
                             S.bad, c->st);
       launch_scale<T>(S.coef, w, n, w, n, n, nrhs, false, c->st);
+    };
+    for (int j = 0; j < m; ++j) {
+      if (check_every > 0 && j > 0 && j % check_every == 0) {
+        LQ_HIP(hipMemcpyAsync(act.data(), S.active, nrhs * sizeof(int), hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        bool run = false;
+        for (int k = 0; k < nrhs; ++k) run = run || act[k];
+        if (!run) break;
+      }
+      if (graph_id && check_every > 0) {
+        // steps j .. j + len - 1, up to the next check
+        const int j0 = j, len = std::min(check_every - j % check_every, m - j);
+        std::vector<uint64_t> key = *graph_id;
+        key.insert(key.end(), {(uint64_t)sizeof(T), (uint64_t)n, (uint64_t)nrhs, (uint64_t)m, (uint64_t)j0,
+                               (uint64_t)len, key_bits(tol), key_bits(Vb), key_bits(Zb), key_bits(sc),
+                               key_bits(S.h1), key_bits(S.h2), key_bits(S.nrm2), key_bits(S.H), key_bits(S.cs),
+                               key_bits(S.sn), key_bits(S.g), key_bits(S.bn), key_bits(S.active), key_bits(S.kk),
+                               key_bits(S.coef), key_bits(S.bad)});
+        hipGraphExec_t ex = chunk_graph(c, key, [&] {
+          for (int jj = j0; jj < j0 + len; ++jj) step(jj);
+        });
+        LQ_HIP(hipGraphLaunch(ex, c->st));
+        j += len - 1;
+        continue;
+      }
+      step(j);
     }
     // x += sum_i y_i (Z_i or V_i)
     launch_arnoldi_solve(m, nrhs, S.H, S.g, S.kk, S.Y, c->st);
@@ -363,19 +436,36 @@ void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, 
   const long long n = (long long)c->cg.nA * c->cg.n2;
   Shifts S = shifts_of(sig, nrhs);
   launch_coarse_g5<T>(c->cg, rc, rhs_buf, nrhs, c->st);
+  // graphs only while the coarse apply is not being timed (its timed launch
+  // records events, which a capture cannot hold).  With graphs the shifts go
+  // to device memory, so the coarse-apply launches are the same for every
+  // solve of this shape and the captured steps can be replayed.
+  const bool graphs = c->p.graphs && g_ktimer_class != KT_COARSE;
+  double *dsig = nullptr;
+  if (graphs) {
+    dsig = c->coarse_sig.get(kMaxRhs);
+    launch_set_shifts(S, nrhs, dsig, c->st);
+  }
   KOps<T> ops;
   const cplx<T> *Qc = mgd<T>(c).Qc.p;
-  ops.apply = [=](const cplx<T> *x, cplx<T> *y) { launch_coarse_apply<T>(c->cg, Qc, x, y, S, nrhs, true, c->st); };
+  // kernel variant for this shape: timed once, before any capture (ec is
+  // overwritten here and zeroed by GMRES)
+  const int variant = tune_coarse_apply<T>(c->cg, Qc, rhs_buf, ec, nrhs, c->st);
+  ops.apply = [=](const cplx<T> *x, cplx<T> *y) {
+    launch_coarse_apply<T>(c->cg, Qc, x, y, S, nrhs, true, c->st, dsig);
+  };
   auto &kw = ckw<T>(c);
   const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
   ops.resid = [=](const cplx<T> *b, const cplx<T> *x, cplx<T> *r) {
-    launch_coarse_apply<T>(c->cg, Qc, x, r, S, nrhs, true, c->st);
+    launch_coarse_apply<T>(c->cg, Qc, x, r, S, nrhs, true, c->st, dsig);
     launch_scale<T>(pm1, r, n, r, n, n, nrhs, false, c->st);                 // r = -A x
     launch_multi_axpy<T>(1, b, 0, n, pp1, r, n, n, nrhs, 1.0, c->st);       // r += b
   };
   int its[kMaxRhs];
+  const std::vector<uint64_t> gid = {key_bits(Qc), key_bits(dsig), (uint64_t)c->cg.nA, (uint64_t)c->cg.n2,
+                                     (uint64_t)variant, key_bits(pm1)};
   gmres_batched<T>(c, kw, n, nrhs, ops, rhs_buf, ec, c->p.coarse_m, c->p.coarse_restarts, c->p.coarse_tol, its,
-                   nullptr, 8);
+                   nullptr, 8, graphs ? &gid : nullptr);
   for (int k = 0; k < nrhs; ++k) c->coarse_iters += its[k];
 }
 
@@ -930,6 +1020,7 @@ int lq_params_default(lq_mg_params *p) {
   p->rqi_solve_restarts = 1;
   p->rqi_deflate = 1;
   p->rqi_start_passes = 0;
+  p->graphs = 0;       // measured: replay gains nothing over direct launches here
   return LQ_OK;
 }
 
@@ -1021,6 +1112,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
     if (p.rqi_block < 1 || p.rqi_block > kMaxRhs) fail(LQ_ERR_ARG, "rqi_block must be in 1..16");
     if (p.rqi_guard < 0) fail(LQ_ERR_ARG, "rqi_guard must be >= 0");
     if (p.rqi_start_passes < 0) fail(LQ_ERR_ARG, "rqi_start_passes must be >= 0");
+    if (p.graphs != 0 && p.graphs != 1) fail(LQ_ERR_ARG, "graphs must be 0 or 1");
     if (p.coarse_m < 1 || p.fgmres_m < 1 || p.sap_mr < 0 || p.post < 0 || p.pre < 0)
       fail(LQ_ERR_ARG, "bad iteration parameters");
     c->have = false;
@@ -1136,9 +1228,9 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
       copy<double>(c, E, c->W.p, (size_t)n_tv_used * V12);
       if (n_v0 > 0) launch_permute<double>(c->g, (const c128 *)V0, E + n_tv_used * V12, n_v0, true, c->st);
     }
-    // with start passes and Rayleigh-Ritz the first generalised Rayleigh-Ritz
-    // step orthonormalises the set; otherwise Alg. 1 starts from orthonormal vectors
-    if (!(c->p.rqi_start_passes > 0 && c->p.rayleigh_ritz)) orthonormalise(c, E, nw);
+    // Alg. 1 starts from orthonormal vectors (also before start passes: the
+    // first multigrid pass then acts on an orthonormal set)
+    orthonormalise(c, E, nw);
     std::vector<double> lam(nw, 0.0), eps(nw, 1.0);
     c128 *SEL = c->sel.get((size_t)Nv * V12);
     // P from the current approximations (Alg. 1: "update v_i in P").  With
@@ -1407,6 +1499,8 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     return done ? LQ_OK : LQ_WARN_NOCONV;
   });
 }
+
+int lq_coarse_variant(int v) { return coarse_force_variant(v) == 0 ? LQ_OK : LQ_ERR_ARG; }
 
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V) {
   if (n < 1 || !A || !w || !V) return LQ_ERR_ARG;

@@ -23,7 +23,7 @@ SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
-            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh"]
+            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -42,7 +42,7 @@ class _Params(C.Structure):
                 ("fgmres_restarts", C.c_int), ("n_init", C.c_int), ("n_setup", C.c_int),
                 ("rqi_block", C.c_int), ("rqi_max_sweeps", C.c_int), ("rqi_solve_tol", C.c_double),
                 ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int), ("rqi_solve_restarts", C.c_int),
-                ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int)]
+                ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int), ("graphs", C.c_int)]
 
 
 class _SolveStats(C.Structure):
@@ -79,6 +79,7 @@ class MGParams:
     rqi_solve_restarts: int | None = None
     rqi_deflate: int | None = None
     rqi_start_passes: int | None = None
+    graphs: int | None = None
 
     def to_c(self, lib) -> _Params:
         p = _Params()
@@ -126,6 +127,7 @@ def load():
         "lq_kernel_timer_start": (i, [i]),
         "lq_kernel_timer_read": (i, [C.POINTER(C.c_longlong), dp, dp]),
         "lq_herm_eigh": (i, [i, vp, vp, vp]),
+        "lq_coarse_variant": (i, [i]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -287,6 +289,13 @@ def kernel_timer_read():
     if rc != 0:
         raise LQError(rc, "lq_kernel_timer_read failed")
     return n.value, ms.value, by.value
+
+
+def coarse_variant(v: int) -> None:
+    """Force coarse-apply kernel v (0..3) for every shape, or -1 for the tuned choice."""
+    rc = load().lq_coarse_variant(int(v))
+    if rc != 0:
+        raise LQError(rc, f"lq_coarse_variant({v}) failed")
 
 
 def herm_eigh(A):

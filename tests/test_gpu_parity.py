@@ -127,9 +127,19 @@ def test_q_apply_full_size_sampled_sites():
     assert relmax(host(y32[0])[:, sites], ref) < 2e-6
 
 
+@pytest.fixture
+def coarse_kernel():
+    from paper_1509_06865_amd import coarse_variant
+    yield coarse_variant
+    coarse_variant(-1)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-6)], ids=["fp64", "fp32"])
-def test_coarse_apply_many_sites(prec, tol):
-    # 8192 coarse sites: the all-rhs-per-workgroup coarse kernel (FP64 or FP32)
+def test_coarse_apply_many_sites(prec, tol, variant, coarse_kernel):
+    # 8192 coarse sites, each of the four coarse-apply kernels (one wave per
+    # (site, rhs); LDS-staged blocks for 4, 8, 16 rhs per pass), FP64 or FP32
+    coarse_kernel(variant)
     dims, agg = (16, 16, 16, 32), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 31)
     lat = Lattice(dims, 1)
@@ -320,6 +330,33 @@ def test_solve_shifted_matches_dense(hier):
         ref = np.linalg.solve(Qd - sig[k] * np.eye(Qd.shape[0]), b[k].ravel())
         assert np.linalg.norm(x[k].ravel() - ref) / np.linalg.norm(ref) < 1e-8
         assert info["relres"][k] < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_coarse_graph_replay_equals_direct_launches(prec):
+    # The coarse GMRES replays its 8-step Arnoldi chunks from captured graphs
+    # (cached per shape and reused across solves, with eager work and host
+    # waits between replays).  Every solve must give the bits of the same
+    # solve with direct launches: 5 shifts, then 3, then the 5 again.
+    from paper_1509_06865_amd import MGParams
+    dims, agg = (8, 8, 8, 16), (2, 2, 2, 2)
+    U = dev(lqsynth.gauge_field(dims, 0.3, 81))
+    tv = dev(lqsynth.gaussian_spinors(8, dims, 82))
+    b = dev(lqsynth.gaussian_spinors(5, dims, 83))
+    sig = [0.0, 0.004, -0.006, 0.008, -0.01]
+    out = {}
+    for graphs in (1, 0):
+        c = _ctx(dims, 1)
+        c.mg_setup(U, -0.2, agg, tv, MGParams(precision=prec, n_setup=2, n_init=1, coarse_m=40, coarse_tol=1e-3,
+                                              coarse_restarts=1, graphs=graphs))
+        x1, i1 = c.mg_solve_shifted(sig, b, 1e-8)
+        x2, _ = c.mg_solve_shifted(sig[:3], b[:3], 1e-8)
+        x3, _ = c.mg_solve_shifted(sig, b, 1e-8)
+        print(graphs, i1)
+        out[graphs] = [host(x1), host(x2), host(x3)]
+    for k in range(3):
+        assert np.array_equal(out[1][k], out[0][k]), k
+    assert np.array_equal(out[1][0], out[1][2])
 
 
 # ------------------------------------------------------------- eigenpairs ----
