@@ -182,15 +182,16 @@ int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c1
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V);
 
 /* ---- coarse-apply kernel choice --------------------------------------------- */
-/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has four
+/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has six
  * kernels: 0 one wavefront per (coarse site, rhs); 1, 2, 3 one workgroup per
  * coarse site with each 2Nv x 2Nv block staged in LDS and applied to 4, 8 or
- * 16 right-hand sides per pass.  By default each coarse solve times the four
- * on its first call for a shape (precision, coarse sites, 2Nv, rhs count,
- * device) and keeps the fastest for the process.  lq_coarse_variant(v) with
- * v in 0..3 forces kernel v for every shape (tests compare them); v = -1
- * returns to the tuned choice.  Process-wide, not thread-safe.
- * Errors: LQ_ERR_ARG for v outside -1..3. */
+ * 16 right-hand sides per pass; 4, 5 as 1, 2 with one workgroup per (coarse
+ * site, chunk of 4 or 8 right-hand sides).  By default each coarse solve
+ * times the six on its first call for a shape (precision, coarse sites, 2Nv,
+ * rhs count, device) and keeps the fastest for the process.
+ * lq_coarse_variant(v) with v in 0..5 forces kernel v for every shape (tests
+ * compare them); v = -1 returns to the tuned choice.  Process-wide, not
+ * thread-safe.  Errors: LQ_ERR_ARG for v outside -1..5. */
 int lq_coarse_variant(int v);
 
 /* ---- kernel timing (measurement of the hot kernels against the roofline) -- */

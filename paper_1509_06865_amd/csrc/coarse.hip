@@ -82,7 +82,9 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
   auto block_ptr = [&](int d) {
     return (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
   };
-  for (int k0 = 0; k0 < nrhs; k0 += KCH) {
+  // right-hand-side chunks of KCH: all of them in this workgroup, or with a
+  // split grid (gridDim.y > 1) chunk y, y + gridDim.y, ...
+  for (int k0 = blockIdx.y * KCH; k0 < nrhs; k0 += KCH * gridDim.y) {
     const int kc = (nrhs - k0 < KCH) ? nrhs - k0 : KCH;
     cplx<T> acc[(KCH + 3) / 4 > 0 ? (KCH + 3) / 4 : 1];
     const int nacc = (kc + rhs_slots - 1) / rhs_slots;
@@ -159,8 +161,10 @@ __global__ void k_set_shifts(Shifts s, int n, double *dst) {
 }
 
 // Variants of the coarse apply: 0 = one wave per (site, rhs); 1..3 = one
-// workgroup per site with the blocks staged in LDS for 4, 8 or 16 rhs per pass.
-constexpr int kCoarseVariants = 4;
+// workgroup per site with the blocks staged in LDS for 4, 8 or 16 rhs per pass;
+// 4, 5 = as 1, 2 with one workgroup per (site, chunk of 4 or 8 rhs), for
+// coarse grids too small to fill the GPU with one workgroup per site.
+constexpr int kCoarseVariants = 6;
 
 template <typename T>
 void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x,
@@ -175,6 +179,14 @@ void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const c
     case 3:
       LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 16>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form,
                 nrhs);
+      break;
+    case 4:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 4>), dim3(cg.nA, (nrhs + 3) / 4), dim3(256), 0, st, cg, Qc, x, y, sig,
+                dsig, g5form, nrhs);
+      break;
+    case 5:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 8>), dim3(cg.nA, (nrhs + 7) / 8), dim3(256), 0, st, cg, Qc, x, y, sig,
+                dsig, g5form, nrhs);
       break;
     default:
       LQ_LAUNCH(kt, (k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, dsig, g5form);

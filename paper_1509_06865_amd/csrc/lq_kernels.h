@@ -123,7 +123,7 @@ int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x,
 // the variant used for a shape: the forced one, else the tuned one, else -1
 template <typename T>
 int coarse_variant(const CoarseGeom &cg, int nrhs);
-// force variant v (0..3) for every shape, or -1 to use the tuned choice; -1 return = bad v
+// force variant v (0..5) for every shape, or -1 to use the tuned choice; -1 return = bad v
 int coarse_force_variant(int v);
 // y_k = g5c x_k (elementwise)
 template <typename T>

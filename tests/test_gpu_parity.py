@@ -134,11 +134,12 @@ def coarse_kernel():
     coarse_variant(-1)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-6)], ids=["fp64", "fp32"])
 def test_coarse_apply_many_sites(prec, tol, variant, coarse_kernel):
-    # 8192 coarse sites, each of the four coarse-apply kernels (one wave per
-    # (site, rhs); LDS-staged blocks for 4, 8, 16 rhs per pass), FP64 or FP32
+    # 8192 coarse sites, each of the six coarse-apply kernels (one wave per
+    # (site, rhs); LDS-staged blocks for 4, 8, 16 rhs per pass, per site or
+    # per (site, chunk of 4 or 8 rhs)), FP64 or FP32; 11 rhs leave a ragged chunk
     coarse_kernel(variant)
     dims, agg = (16, 16, 16, 32), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 31)
