@@ -29,9 +29,11 @@ __device__ inline double block_sum(double v, double *lds) {
   return r;
 }
 
-// Stage 1: partial[g*kDotGroup + i][k][chunk].  Rows past nv read row nv - 1
-// and are dropped, so the loads carry no branches and stay in flight together.
-template <typename T>
+// Stage 1: partial[row][k][chunk] for the rows g*G .. g*G + G - 1 of group g.
+// Rows past nv read row nv - 1 and are dropped, so the loads carry no branches
+// and stay in flight together; the launcher picks G (1, 2, 4, 8) as the
+// smallest power of two covering nv, capped at kDotGroup, so few are wasted.
+template <typename T, int G>
 __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx<T> *__restrict__ vbase,
                                                               long long vstride, long long rstride,
                                                               const cplx<T> *__restrict__ w, long long wstride,
@@ -41,31 +43,31 @@ __global__ void __launch_bounds__(kDotThreads) k_dots_partial(int nv, const cplx
   const int chunk = blockIdx.x, k = blockIdx.y, grp = blockIdx.z;
   const int nchunks = gridDim.x, nrhs = gridDim.y;
   if (active && !active[k]) {
-    if (threadIdx.x < kDotGroup && grp * kDotGroup + (int)threadIdx.x < nv)
-      partial[((long long)(grp * kDotGroup + threadIdx.x) * nrhs + k) * nchunks + chunk] = c128{0, 0};
+    if (threadIdx.x < G && grp * G + (int)threadIdx.x < nv)
+      partial[((long long)(grp * G + threadIdx.x) * nrhs + k) * nchunks + chunk] = c128{0, 0};
     return;
   }
   const long long per = (n + nchunks - 1) / nchunks;
   const long long lo = chunk * per, hi = (lo + per < n) ? lo + per : n;
   const cplx<T> *wk = w + k * wstride;
-  double re[kDotGroup], im[kDotGroup];
+  double re[G], im[G];
 #pragma unroll
-  for (int i = 0; i < kDotGroup; ++i) { re[i] = 0; im[i] = 0; }
-  const int i0 = grp * kDotGroup;
-  const cplx<T> *vk[kDotGroup];
+  for (int i = 0; i < G; ++i) { re[i] = 0; im[i] = 0; }
+  const int i0 = grp * G;
+  const cplx<T> *vk[G];
 #pragma unroll
-  for (int i = 0; i < kDotGroup; ++i) vk[i] = vbase + (long long)(i0 + i < nv ? i0 + i : nv - 1) * vstride + k * rstride;
+  for (int i = 0; i < G; ++i) vk[i] = vbase + (long long)(i0 + i < nv ? i0 + i : nv - 1) * vstride + k * rstride;
   for (long long e = lo + threadIdx.x; e < hi; e += kDotThreads) {
     const cplx<T> wv = wk[e];
 #pragma unroll
-    for (int i = 0; i < kDotGroup; ++i) {
+    for (int i = 0; i < G; ++i) {
       const cplx<T> v = vk[i][e];
       re[i] += (double)v.re * wv.re + (double)v.im * wv.im;
       im[i] += (double)v.re * wv.im - (double)v.im * wv.re;
     }
   }
 #pragma unroll
-  for (int i = 0; i < kDotGroup; ++i) {
+  for (int i = 0; i < G; ++i) {
     if (i0 + i >= nv) break;
     double sr = block_sum(re[i], lds);
     double si = block_sum(im[i], lds);
@@ -263,10 +265,26 @@ void launch_dots(int nv, const cplx<T> *vbase, long long vstride, long long rstr
   int nchunks = (int)((n + 4 * kDotThreads - 1) / (4 * kDotThreads));
   if (nchunks > kDotChunks) nchunks = kDotChunks;
   if (nchunks < 1) nchunks = 1;
-  const int groups = (nv + kDotGroup - 1) / kDotGroup;
   c128 *partial = scratch;
-  hipLaunchKernelGGL((k_dots_partial<T>), dim3(nchunks, nrhs, groups), dim3(kDotThreads), 0, st, nv, vbase,
-                     vstride, rstride, w, wstride, n, partial, active);
+  const int G = (nv > 4) ? kDotGroup : (nv > 2) ? 4 : nv;      // 1, 2, 4 or 8
+  const dim3 grid(nchunks, nrhs, (nv + G - 1) / G);
+  switch (G) {
+    case 1:
+      hipLaunchKernelGGL((k_dots_partial<T, 1>), grid, dim3(kDotThreads), 0, st, nv, vbase, vstride, rstride, w,
+                         wstride, n, partial, active);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_dots_partial<T, 2>), grid, dim3(kDotThreads), 0, st, nv, vbase, vstride, rstride, w,
+                         wstride, n, partial, active);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_dots_partial<T, 4>), grid, dim3(kDotThreads), 0, st, nv, vbase, vstride, rstride, w,
+                         wstride, n, partial, active);
+      break;
+    default:
+      hipLaunchKernelGGL((k_dots_partial<T, kDotGroup>), grid, dim3(kDotThreads), 0, st, nv, vbase, vstride,
+                         rstride, w, wstride, n, partial, active);
+  }
   LQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_dots_final, dim3(nv * nrhs), dim3(64), 0, st, partial, nchunks, out);
   LQ_HIP(hipGetLastError());
