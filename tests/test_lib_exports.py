@@ -55,6 +55,17 @@ def test_create_rejects_bad_arguments():
     assert lib.lq_create(ctypes.byref(h), good, 0, None) == -1
 
 
+def test_coarse_variant_switch_checks_its_argument():
+    # host-only: forcing a coarse-apply kernel accepts -1 (tuned) and 0..5
+    from paper_1509_06865_amd.lqmg import LQError, coarse_variant
+    for v in (-2, 6, 100):
+        with pytest.raises(LQError):
+            coarse_variant(v)
+    for v in range(6):
+        coarse_variant(v)
+    coarse_variant(-1)
+
+
 @pytest.mark.parametrize("n,kind", [(1, "rand"), (7, "rand"), (64, "degen"), (132, "rand"), (132, "degen")])
 def test_dense_hermitian_eigensolver_matches_numpy(n, kind):
     # the host eigensolver of the Rayleigh-Ritz step, against numpy's LAPACK,
