@@ -105,7 +105,10 @@ typedef struct {
   int sweeps;           /* passes of Alg. 1 over the unconverged vectors */
   int solves;           /* shifted systems solved */
   int fgmres_iters;     /* total FGMRES iterations */
-  int p_rebuilds;       /* interpolation / coarse-operator rebuilds */
+  int p_rebuilds;       /* interpolation / coarse-operator rebuilds (not counted:
+                           rebuilds in which the approximations were linearly
+                           dependent on some aggregate, whose block of P then
+                           kept its previous columns) */
   double t_solve, t_ortho, t_rebuild, t_rq;   /* seconds per phase */
 } lq_rqi_stats;
 

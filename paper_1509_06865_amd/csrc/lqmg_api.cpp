@@ -553,8 +553,11 @@ template <typename T> void build_coarse(lq_ctx *c, DevBuf<cplx<T>> &parts, DevBu
     }
 }
 
-// P and Q_c from the FP64 fields src [Nv][12][V] (blocked)
-void rebuild(lq_ctx *c, const c128 *src) {
+// P and Q_c from the FP64 fields src [Nv][12][V] (blocked).  Fields that are
+// linearly dependent on some aggregate half are an error, unless keep_dependent:
+// then those blocks of P keep their previous columns (the other blocks are
+// rebuilt, P stays orthonormal and gamma5-split) and the call returns false.
+bool rebuild(lq_ctx *c, const c128 *src, bool keep_dependent = false) {
   const size_t nP = (size_t)c->Nv * 12 * c->g.V;
   int *st = c->status.get(1);
   LQ_HIP(hipMemsetAsync(st, 0, sizeof(int), c->st));
@@ -563,7 +566,7 @@ void rebuild(lq_ctx *c, const c128 *src) {
   int h_st = 0;
   LQ_HIP(hipMemcpyAsync(&h_st, st, sizeof(int), hipMemcpyDeviceToHost, c->st));
   sync(c);
-  if (h_st) fail(LQ_ERR_NUMERIC, "test vectors are linearly dependent on an aggregate");
+  if (h_st && !keep_dependent) fail(LQ_ERR_NUMERIC, "test vectors are linearly dependent on an aggregate");
   if (c->p.precision == LQ_PREC_FP64) {
     copy<double>(c, c->d64.P.get(nP), P64, nP);
     build_coarse<double>(c, c->parts64, c->pc64);
@@ -572,6 +575,7 @@ void rebuild(lq_ctx *c, const c128 *src) {
     build_coarse<float>(c, c->parts32, c->pc32);
   }
   sync(c);
+  return h_st == 0;
 }
 
 // Gram-Schmidt (twice) of n fields in place, in index order; FP64.
@@ -1256,8 +1260,9 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
       }
       for (size_t q = 0; q < idx.size(); ++q) copy<double>(c, SEL + q * V12, E + idx[q] * V12, V12);
       for (int q = (int)idx.size(); q < Nv; ++q) copy<double>(c, SEL + q * V12, c->W.p + q * V12, V12);
-      rebuild(c, SEL);
-      S.p_rebuilds++;
+      // approximations that are dependent on an aggregate (exactly degenerate
+      // smooth modes) leave that aggregate's columns of P as they were
+      if (rebuild(c, SEL, true)) S.p_rebuilds++;
       S.t_rebuild += now() - t0;
     };
     // the n_eig vectors with smallest |lambda| have converged

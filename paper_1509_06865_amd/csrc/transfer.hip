@@ -150,7 +150,10 @@ template <typename T> constexpr int transfer_group() { return sizeof(T) == 4 ? 4
 // Cholesky-QR, applied twice, of the (6*bvol) x Nv local matrix of aggregate
 // A and gamma5 half h.  Gram G = W^dag W, G = L L^dag, P = W L^-dag; the QR
 // factor with positive diagonal is unique, so this is the same orthonormal
-// basis that Gram-Schmidt in vector order produces.
+// basis that Gram-Schmidt in vector order produces.  If the columns are
+// linearly dependent on the aggregate half (a pivot below 1e-13 of its
+// diagonal), the workgroup writes nothing, so that block of P keeps its
+// previous columns, and raises *status.
 constexpr int kMaxNv = 32;
 __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict__ W, int Nv,
                                                  c128 *__restrict__ P, int *status) {
@@ -203,7 +206,7 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict_
         const double gjj = L[jj][jj].re;
         double d = gjj;
         for (int k = 0; k < jj; ++k) d -= norm2(L[jj][k]);
-        if (!(d > 1e-13 * gjj) || !(gjj > 0)) { bad = 1; d = 1.0; }
+        if (!(d > 1e-13 * gjj) || !(gjj > 0)) { bad = 1; break; }
         const double ljj = sqrt(d);
         L[jj][jj] = c128{ljj, 0};
         for (int i = jj + 1; i < Nv; ++i) {
@@ -214,6 +217,7 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict_
       }
     }
     __syncthreads();
+    if (bad) break;                    // the same for the whole workgroup: keep the old block
     // P rows: p = w L^-dag  <=>  sum_{i<=j} p_i conj(L[j][i]) = w_j
     if (active) {
       for (int r = 0; r < 6; ++r) {

@@ -397,6 +397,45 @@ def test_rqi_lowest_eight_match_dense(name, prec, nv):
     assert np.abs(G - np.eye(8)).max() < 1e-10
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_rqi_exactly_degenerate_free_field_shell(prec):
+    # The method's degenerate case: unit links on a periodic 4^4 lattice.  The
+    # closed-form free spectrum (sec. 2's Q with U = 1) has its 12 lowest
+    # modes at lambda = +-m0 exactly (zero momentum, 6 of each sign), the next
+    # at +-sqrt((m0 + 1)^2 + 1).  The eigenvectors inside the shell are not
+    # unique; what is: the eigenvalues, each residual, orthonormality, and the
+    # span (the projector onto the shell: constant fields of each gamma5 half).
+    dims, m0 = (4, 4, 4, 4), 0.05
+    lat = Lattice(dims, 1)
+    V = lat.V
+    U = np.zeros((4, 3, 3, V), dtype=np.complex128)
+    for a in range(3):
+        U[:, a, a, :] = 1.0
+    U = U.reshape(4, 9, V)
+    from paper_1509_06865_amd import MGParams
+    c = _ctx(dims, 1)
+    c.mg_setup(dev(U), m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(8, dims, 111)),
+               MGParams(precision=prec, coarse_m=128, coarse_tol=1e-8, coarse_restarts=2, n_setup=4,
+                        rqi_block=4, rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1))
+    V0 = dev(lqsynth.gaussian_spinors(12 + 4 - 8, dims, 112))
+    lam, Vd, res, info = c.rqi_lowmodes(12, 1e-10, V0=V0)
+    assert info["converged"], info
+    lam = np.array(lam)
+    # all |lambda| equal: rounding decides the order of the two signs
+    ref = np.array([-m0] * 6 + [m0] * 6)
+    assert np.abs(np.sort(lam) - ref).max() < 1e-12
+    Vh = host(Vd)
+    Qv = WilsonOp(U, m0, lat).Q(Vh)
+    for i in range(12):
+        assert np.linalg.norm(Qv[i] - lam[i] * Vh[i]) <= 2e-10
+    G = np.einsum("ian,jan->ij", Vh.conj(), Vh)
+    assert np.abs(G - np.eye(12)).max() < 1e-10
+    # the shell is the space of site-constant fields: each returned vector is
+    # its own average over the sites (to the residual's accuracy)
+    avg = Vh.mean(axis=2, keepdims=True)
+    assert np.abs(Vh - avg).max() < 1e-9
+
+
 def test_rqi_benchmark_workload_returns_exact_pairs():
     # The benchmark's configuration at full size (16^4, 50 lowest pairs,
     # Nv = 20, guard 70, 6 start passes, blocks of 16 shifted solves): every
