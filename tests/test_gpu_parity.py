@@ -207,6 +207,13 @@ def test_argument_and_state_errors_are_reported():
         c.mg_solve_shifted([0.0] * 17, dev(lqsynth.gaussian_spinors(17, dims, 74)), 1e-6)   # > 16 shifts
     with pytest.raises(LQError):
         c.rqi_lowmodes(4, 1e-10, V0=dev(lqsynth.gaussian_spinors(5, dims, 75)))             # wrong V0 count
+    # empty inputs: no fields, no shifts, no eigenpairs
+    with pytest.raises(LQError):
+        c.q_apply(U, m0, x[:0])
+    with pytest.raises(LQError):
+        c.mg_solve_shifted([], x[:0], 1e-6)
+    with pytest.raises(LQError):
+        c.rqi_lowmodes(0, 1e-10)
     # the context stays usable after the errors
     y = host(c.q_apply(U, m0, x))
     ref = WilsonOp(lqsynth.gauge_field(dims, eps, seed), m0, Lattice(dims, bc)).Q(host(x))
