@@ -93,6 +93,11 @@ typedef struct {
                            graph, cached per shape; same kernels and bitwise the
                            same results as 0 (direct launches, the default).
                            Off while LQ_KT_COARSE is timed */
+  int coarse_bf16;      /* LQ_PREC_MIXED only: 1 = the FP32 multigrid reads Q_c
+                           from a bfloat16 copy (8-bit mantissa, FP32 arithmetic
+                           and accumulation): half the coarse operator's bytes,
+                           a coarse operator accurate to ~2^-9 relative; the FP64
+                           outer FGMRES keeps the solves exact.  0 = FP32 Q_c */
 } lq_mg_params;
 
 typedef struct {
@@ -229,7 +234,9 @@ int mg_get_coarse(lq_ctx *ctx, lq_c128 *Qc);
 int mg_restrict(lq_ctx *ctx, int n, const lq_c128 *f, lq_c128 *c);
 /* Prolongation f = P c (shapes as above). */
 int mg_prolong(lq_ctx *ctx, int n, const lq_c128 *c, lq_c128 *f);
-/* y = (Q_c - sigma[k]) x[k] on coarse vectors [n][nA][2Nv]; sigma host. */
+/* y = (Q_c - sigma[k]) x[k] on coarse vectors [n][nA][2Nv]; sigma host.  In
+ * mixed precision this is the stored FP32 (or, with coarse_bf16, bfloat16)
+ * operator applied in FP32. */
 int mg_coarse_apply(lq_ctx *ctx, int n, const double *sigma, const lq_c128 *x,
                     lq_c128 *y);
 /* z = smoother applied to r for shifts sigma (steps as in the parameters'

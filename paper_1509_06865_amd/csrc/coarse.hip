@@ -20,9 +20,28 @@ __device__ inline int cnbr(const CoarseGeom &cg, int A, int mu, int step) {
   return a[0] + cg.nb[0] * (a[1] + cg.nb[1] * (a[2] + cg.nb[2] * a[3]));
 }
 
+// Block entries as read by the kernels: FP32/FP64 as stored, or bfloat16
+// widened to FP32 (its bits are the upper half of the FP32 number).
+template <typename T> __device__ inline cplx<T> qval(const cplx<T> &v) { return v; }
+__device__ inline cplx<float> qval(const bf16c &v) {
+  return mk<float>(__uint_as_float((unsigned)v.re << 16), __uint_as_float((unsigned)v.im << 16));
+}
+
+// FP32 -> bfloat16, round to nearest, ties to even; NaN stays NaN.
+__device__ inline unsigned short to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_to_bf16(const cplx<float> *__restrict__ in, bf16c *__restrict__ out, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = bf16c{to_bf16(in[e].re), to_bf16(in[e].im)};
+}
+
 // One workgroup (one wave) per (coarse site, rhs); thread i computes row i.
-template <typename T>
-__global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
+template <typename T, typename QT>
+__global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const QT *__restrict__ Qc,
                                                      const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
                                                      Shifts sig, const double *__restrict__ dsig, bool g5form) {
   __shared__ cplx<T> xs[9][64];
@@ -40,13 +59,13 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T
   // self and forward blocks: row i of Qc[A][d]
   cplx<T> acc = mk<T>(0, 0);
   for (int d = 0; d < 5; ++d) {
-    const cplx<T> *M = Qc + ((long long)A * 5 + d) * bs + (long long)i * n2;
-    for (int j = 0; j < n2; ++j) acc = acc + M[j] * xs[d][j];
+    const QT *M = Qc + ((long long)A * 5 + d) * bs + (long long)i * n2;
+    for (int j = 0; j < n2; ++j) acc = acc + qval(M[j]) * xs[d][j];
   }
   // backward: sum_j conj(Qc[A-mu][1+mu][j][i]) x_{A-mu}[j]
   for (int mu = 0; mu < 4; ++mu) {
-    const cplx<T> *M = Qc + ((long long)nb[5 + mu] * 5 + 1 + mu) * bs + i;
-    for (int j = 0; j < n2; ++j) acc = acc + cmul_conj(M[(long long)j * n2], xs[5 + mu][j]);
+    const QT *M = Qc + ((long long)nb[5 + mu] * 5 + 1 + mu) * bs + i;
+    for (int j = 0; j < n2; ++j) acc = acc + cmul_conj(qval(M[(long long)j * n2]), xs[5 + mu][j]);
   }
   acc = acc - (T)(dsig ? dsig[k] : sig.s[k]) * xs[0][i];
   if (g5form && i >= n2 / 2) acc = -acc;
@@ -62,8 +81,8 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeom cg, const cplx<T
 constexpr int kCoarseMaxN2 = 64;
 constexpr int kCoarsePerThread = (kCoarseMaxN2 * kCoarseMaxN2 + 255) / 256;
 
-template <typename T, int KCH>
-__global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const cplx<T> *__restrict__ Qc,
+template <typename T, typename QT, int KCH>
+__global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const QT *__restrict__ Qc,
                                                             const cplx<T> *__restrict__ xin,
                                                             cplx<T> *__restrict__ yout, Shifts sig,
                                                             const double *__restrict__ dsig, bool g5form, int nrhs) {
@@ -79,7 +98,7 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
   const int rows_per = n2;                          // threads per rhs
   const int rhs_slots = 256 / rows_per;             // rhs handled at once
   const int i = t % rows_per, ks = t / rows_per;
-  auto block_ptr = [&](int d) {
+  auto block_ptr = [&](int d) -> const QT * {
     return (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
   };
   // right-hand-side chunks of KCH: all of them in this workgroup, or with a
@@ -91,11 +110,11 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
     for (int a = 0; a < (int)(sizeof(acc) / sizeof(acc[0])); ++a) acc[a] = mk<T>(0, 0);
     cplx<T> pre[kCoarsePerThread];
     {
-      const cplx<T> *M = block_ptr(0);
+      const QT *M = block_ptr(0);
 #pragma unroll
       for (int q = 0; q < kCoarsePerThread; ++q) {
         const int e = t + 256 * q;
-        pre[q] = (e < n2 * n2) ? M[e] : mk<T>(0, 0);
+        pre[q] = (e < n2 * n2) ? qval(M[e]) : mk<T>(0, 0);
       }
     }
     for (int d = 0; d < 9; ++d) {
@@ -114,11 +133,11 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
       }
       __syncthreads();
       if (d + 1 < 9) {
-        const cplx<T> *M = block_ptr(d + 1);
+        const QT *M = block_ptr(d + 1);
 #pragma unroll
         for (int q = 0; q < kCoarsePerThread; ++q) {
           const int e = t + 256 * q;
-          pre[q] = (e < n2 * n2) ? M[e] : mk<T>(0, 0);
+          pre[q] = (e < n2 * n2) ? qval(M[e]) : mk<T>(0, 0);
         }
       }
       if (i < n2)
@@ -166,37 +185,40 @@ __global__ void k_set_shifts(Shifts s, int n, double *dst) {
 // coarse grids too small to fill the GPU with one workgroup per site.
 constexpr int kCoarseVariants = 6;
 
-template <typename T>
-void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x,
+template <typename T, typename QT>
+void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const QT *Qc, const cplx<T> *x,
                            cplx<T> *y, const Shifts &sig, const double *dsig, int nrhs, bool g5form, hipStream_t st) {
   switch (v) {
     case 1:
-      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 4>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form, nrhs);
-      break;
-    case 2:
-      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 8>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form, nrhs);
-      break;
-    case 3:
-      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 16>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form,
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 4>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form,
                 nrhs);
       break;
+    case 2:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 8>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form,
+                nrhs);
+      break;
+    case 3:
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 16>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig,
+                g5form, nrhs);
+      break;
     case 4:
-      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 4>), dim3(cg.nA, (nrhs + 3) / 4), dim3(256), 0, st, cg, Qc, x, y, sig,
-                dsig, g5form, nrhs);
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 4>), dim3(cg.nA, (nrhs + 3) / 4), dim3(256), 0, st, cg, Qc, x, y,
+                sig, dsig, g5form, nrhs);
       break;
     case 5:
-      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, 8>), dim3(cg.nA, (nrhs + 7) / 8), dim3(256), 0, st, cg, Qc, x, y, sig,
-                dsig, g5form, nrhs);
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 8>), dim3(cg.nA, (nrhs + 7) / 8), dim3(256), 0, st, cg, Qc, x, y,
+                sig, dsig, g5form, nrhs);
       break;
     default:
-      LQ_LAUNCH(kt, (k_coarse_apply<T>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, dsig, g5form);
+      LQ_LAUNCH(kt, (k_coarse_apply<T, QT>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, dsig, g5form);
   }
   LQ_HIP(hipGetLastError());
 }
 
-// The tuned variant per (precision, coarse sites, 2 Nv, nrhs, device).
+// The tuned variant per (arithmetic and storage precision, coarse sites, 2 Nv,
+// nrhs, device).
 struct CoarseTuneKey {
-  int tsize, nA, n2, nrhs, dev;
+  int tsize, nA, n2, nrhs, dev;       // tsize: 100 * sizeof(T) + sizeof(QT)
   bool operator<(const CoarseTuneKey &o) const {
     return std::tie(tsize, nA, n2, nrhs, dev) < std::tie(o.tsize, o.nA, o.n2, o.nrhs, o.dev);
   }
@@ -220,21 +242,29 @@ int coarse_force_variant(int v) {
   return 0;
 }
 
-template <typename T>
-int coarse_variant(const CoarseGeom &cg, int nrhs) {
+template <typename T, typename QT> int storage_code() { return 100 * (int)sizeof(T) + (int)sizeof(QT); }
+
+template <typename T, typename QT>
+int coarse_variant_q(const CoarseGeom &cg, int nrhs) {
   std::lock_guard<std::mutex> lk(g_coarse_mu);
   if (g_coarse_force >= 0) return g_coarse_force;
-  auto it = g_coarse_choice.find(coarse_key(cg, sizeof(T), nrhs));
+  auto it = g_coarse_choice.find(coarse_key(cg, storage_code<T, QT>(), nrhs));
   return it == g_coarse_choice.end() ? -1 : it->second;
+}
+
+template <typename T>
+int coarse_variant(const CoarseGeom &cg, int nrhs) {
+  return coarse_variant_q<T, cplx<T>>(cg, nrhs);
 }
 
 // Time every variant on the caller's operands (y is overwritten) and keep the
 // fastest for this shape: one warm-up and three timed launches each, on the
 // stream, outside any graph capture.  A shape already tuned is left alone.
-template <typename T>
-int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, int nrhs,
-                      hipStream_t st) {
-  if (coarse_variant<T>(cg, nrhs) >= 0) return coarse_variant<T>(cg, nrhs);
+template <typename T, typename QT>
+int tune_coarse_apply_q(const CoarseGeom &cg, const QT *Qc, const cplx<T> *x, cplx<T> *y, int nrhs,
+                        hipStream_t st) {
+  const int known = coarse_variant_q<T, QT>(cg, nrhs);
+  if (known >= 0) return known;
   Shifts z{};
   KTimerScope off(KT_COUNT, 0.0);     // never a selected class: untimed
   hipEvent_t e0, e1;
@@ -243,9 +273,9 @@ int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x,
   int best = 0;
   float tbest = 1e30f;
   for (int v = 0; v < kCoarseVariants; ++v) {
-    coarse_launch_variant<T>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
+    coarse_launch_variant<T, QT>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
     LQ_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < 3; ++r) coarse_launch_variant<T>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
+    for (int r = 0; r < 3; ++r) coarse_launch_variant<T, QT>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
     LQ_HIP(hipEventRecord(e1, st));
     LQ_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -255,8 +285,18 @@ int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x,
   LQ_HIP(hipEventDestroy(e0));
   LQ_HIP(hipEventDestroy(e1));
   std::lock_guard<std::mutex> lk(g_coarse_mu);
-  g_coarse_choice[coarse_key(cg, sizeof(T), nrhs)] = best;
+  g_coarse_choice[coarse_key(cg, storage_code<T, QT>(), nrhs)] = best;
   return best;
+}
+
+template <typename T>
+int tune_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, int nrhs,
+                      hipStream_t st) {
+  return tune_coarse_apply_q<T, cplx<T>>(cg, Qc, x, y, nrhs, st);
+}
+
+int tune_coarse_apply_bf16(const CoarseGeom &cg, const bf16c *Qc, const c64 *x, c64 *y, int nrhs, hipStream_t st) {
+  return tune_coarse_apply_q<float, bf16c>(cg, Qc, x, y, nrhs, st);
 }
 
 void launch_set_shifts(const Shifts &s, int n, double *dst, hipStream_t st) {
@@ -264,19 +304,37 @@ void launch_set_shifts(const Shifts &s, int n, double *dst, hipStream_t st) {
   LQ_HIP(hipGetLastError());
 }
 
-template <typename T>
-void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig,
-                         int nrhs, bool g5form, hipStream_t st, const double *dsig) {
+void launch_to_bf16(const c64 *in, bf16c *out, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n, 256)), dim3(256), 0, st, in, out, n);
+  LQ_HIP(hipGetLastError());
+}
+
+template <typename T, typename QT>
+void coarse_apply_q(const CoarseGeom &cg, const QT *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig, int nrhs,
+                    bool g5form, hipStream_t st, const double *dsig) {
   // algorithmic bytes: the 5 stored blocks per site once, x in and y out per field
-  KTimerScope kt(KT_COARSE, ((double)cg.nA * 5 * cg.n2 * cg.n2 + 2.0 * nrhs * cg.nA * cg.n2) * sizeof(cplx<T>));
-  int v = coarse_variant<T>(cg, nrhs);
+  KTimerScope kt(KT_COARSE, (double)cg.nA * 5 * cg.n2 * cg.n2 * sizeof(QT) +
+                                2.0 * nrhs * cg.nA * cg.n2 * sizeof(cplx<T>));
+  int v = coarse_variant_q<T, QT>(cg, nrhs);
   if (v < 0) {
     // untuned shape: few coarse sites (< 1024, e.g. 256 at 16^4 with 4^4
     // aggregates) keep one wave per (site, rhs); many sites stage each block
     // once for all rhs
     v = (nrhs >= 4 && cg.nA >= 1024) ? (sizeof(T) == 4 ? 3 : 2) : 0;
   }
-  coarse_launch_variant<T>(v, kt, cg, Qc, x, y, sig, dsig, nrhs, g5form, st);
+  coarse_launch_variant<T, QT>(v, kt, cg, Qc, x, y, sig, dsig, nrhs, g5form, st);
+}
+
+template <typename T>
+void launch_coarse_apply(const CoarseGeom &cg, const cplx<T> *Qc, const cplx<T> *x, cplx<T> *y, const Shifts &sig,
+                         int nrhs, bool g5form, hipStream_t st, const double *dsig) {
+  coarse_apply_q<T, cplx<T>>(cg, Qc, x, y, sig, nrhs, g5form, st, dsig);
+}
+
+void launch_coarse_apply_bf16(const CoarseGeom &cg, const bf16c *Qc, const c64 *x, c64 *y, const Shifts &sig,
+                              int nrhs, bool g5form, hipStream_t st, const double *dsig) {
+  coarse_apply_q<float, bf16c>(cg, Qc, x, y, sig, nrhs, g5form, st, dsig);
 }
 
 template <typename T>

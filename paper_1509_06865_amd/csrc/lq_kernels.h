@@ -105,6 +105,16 @@ struct CoarseGeom {
   int nA;          // coarse sites
   int n2;          // 2 * Nv unknowns per coarse site
 };
+// A complex number stored as two bfloat16 (the upper 16 bits of an IEEE FP32):
+// the optional storage of the FP32 coarse operator.
+struct bf16c { unsigned short re, im; };
+// out = bf16 of in (round to nearest even), n complex numbers
+void launch_to_bf16(const cplx<float> *in, bf16c *out, long long n, hipStream_t st);
+// as launch_coarse_apply<float> with Q_c stored in bfloat16 (FP32 arithmetic)
+void launch_coarse_apply_bf16(const CoarseGeom &cg, const bf16c *Qc, const cplx<float> *x, cplx<float> *y,
+                              const Shifts &sig, int nrhs, bool g5form, hipStream_t st, const double *dsig = nullptr);
+int tune_coarse_apply_bf16(const CoarseGeom &cg, const bf16c *Qc, const cplx<float> *x, cplx<float> *y, int nrhs,
+                           hipStream_t st);
 // y_k = g5c^e (Q_c - sigma_k) x_k (e = 1 if gamma5c form); vectors [nrhs][nA][n2].
 // sigma_k is read from the device array dsig[k] when dsig is given (a launch
 // whose arguments do not change with the shifts, as graph replay needs), else

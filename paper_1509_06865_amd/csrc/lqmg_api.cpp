@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace lq;
@@ -154,6 +155,7 @@ struct lq_ctx {
   DevBuf<c128> defl_tmp, defl_u, defl_r;   // Galerkin correction work           // Rayleigh-Ritz: gathered unconverged vectors
   DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
   DevBuf<double> coarse_sig;        // shifts of the current coarse solve [kMaxRhs]
+  DevBuf<bf16c> QcB;                // the FP32 Q_c in bfloat16 (coarse_bf16)
   int coarse_iters = 0;
   // captured coarse-GMRES chunks, keyed by shape, step range and every pointer
   // they use; cap_st is the private stream they are captured on
@@ -448,21 +450,38 @@ void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, 
   }
   KOps<T> ops;
   const cplx<T> *Qc = mgd<T>(c).Qc.p;
-  // kernel variant for this shape: timed once, before any capture (ec is
-  // overwritten here and zeroed by GMRES)
-  const int variant = tune_coarse_apply<T>(c->cg, Qc, rhs_buf, ec, nrhs, c->st);
-  ops.apply = [=](const cplx<T> *x, cplx<T> *y) {
+  // the FP32 cycle may read Q_c from its bfloat16 copy (FP32 arithmetic)
+  const bf16c *QcB = nullptr;
+  if constexpr (std::is_same<T, float>::value)
+    if (c->p.coarse_bf16) QcB = c->QcB.p;
+  auto capply = [=](const cplx<T> *x, cplx<T> *y) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (QcB) {
+        launch_coarse_apply_bf16(c->cg, QcB, x, y, S, nrhs, true, c->st, dsig);
+        return;
+      }
+    }
     launch_coarse_apply<T>(c->cg, Qc, x, y, S, nrhs, true, c->st, dsig);
   };
+  // kernel variant for this shape: timed once, before any capture (ec is
+  // overwritten here and zeroed by GMRES)
+  int variant;
+  if constexpr (std::is_same<T, float>::value)
+    variant = QcB ? tune_coarse_apply_bf16(c->cg, QcB, rhs_buf, ec, nrhs, c->st)
+                  : tune_coarse_apply<T>(c->cg, Qc, rhs_buf, ec, nrhs, c->st);
+  else
+    variant = tune_coarse_apply<T>(c->cg, Qc, rhs_buf, ec, nrhs, c->st);
+  ops.apply = capply;
   auto &kw = ckw<T>(c);
   const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
   ops.resid = [=](const cplx<T> *b, const cplx<T> *x, cplx<T> *r) {
-    launch_coarse_apply<T>(c->cg, Qc, x, r, S, nrhs, true, c->st, dsig);
+    capply(x, r);
     launch_scale<T>(pm1, r, n, r, n, n, nrhs, false, c->st);                 // r = -A x
     launch_multi_axpy<T>(1, b, 0, n, pp1, r, n, n, nrhs, 1.0, c->st);       // r += b
   };
   int its[kMaxRhs];
-  const std::vector<uint64_t> gid = {key_bits(Qc), key_bits(dsig), (uint64_t)c->cg.nA, (uint64_t)c->cg.n2,
+  const std::vector<uint64_t> gid = {QcB ? key_bits(QcB) : key_bits(Qc), key_bits(dsig), (uint64_t)c->cg.nA,
+                                     (uint64_t)c->cg.n2,
                                      (uint64_t)variant, key_bits(pm1)};
   gmres_batched<T>(c, kw, n, nrhs, ops, rhs_buf, ec, c->p.coarse_m, c->p.coarse_restarts, c->p.coarse_tol, its,
                    nullptr, 8, graphs ? &gid : nullptr);
@@ -573,6 +592,10 @@ bool rebuild(lq_ctx *c, const c128 *src, bool keep_dependent = false) {
   } else {
     launch_convert<float, double>(P64, c->d32.P.get(nP), (long long)nP, c->st);
     build_coarse<float>(c, c->parts32, c->pc32);
+    if (c->p.coarse_bf16) {
+      const long long nq = (long long)c->cg.nA * 5 * c->cg.n2 * c->cg.n2;
+      launch_to_bf16(c->d32.Qc.p, c->QcB.get((size_t)nq), nq, c->st);
+    }
   }
   sync(c);
   return h_st == 0;
@@ -1025,6 +1048,7 @@ int lq_params_default(lq_mg_params *p) {
   p->rqi_deflate = 1;
   p->rqi_start_passes = 0;
   p->graphs = 0;       // measured: replay gains nothing over direct launches here
+  p->coarse_bf16 = 0;
   return LQ_OK;
 }
 
@@ -1117,6 +1141,8 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
     if (p.rqi_guard < 0) fail(LQ_ERR_ARG, "rqi_guard must be >= 0");
     if (p.rqi_start_passes < 0) fail(LQ_ERR_ARG, "rqi_start_passes must be >= 0");
     if (p.graphs != 0 && p.graphs != 1) fail(LQ_ERR_ARG, "graphs must be 0 or 1");
+    if (p.coarse_bf16 != 0 && p.coarse_bf16 != 1) fail(LQ_ERR_ARG, "coarse_bf16 must be 0 or 1");
+    if (p.coarse_bf16 && p.precision != LQ_PREC_MIXED) fail(LQ_ERR_ARG, "coarse_bf16 needs LQ_PREC_MIXED");
     if (p.coarse_m < 1 || p.fgmres_m < 1 || p.sap_mr < 0 || p.post < 0 || p.pre < 0)
       fail(LQ_ERR_ARG, "bad iteration parameters");
     c->have = false;
@@ -1632,7 +1658,10 @@ int mg_coarse_apply(lq_ctx *c, int n, const double *sigma, const lq_c128 *x, lq_
     } else {
       c64 *a = c->c32b.get((size_t)2 * n * nc);
       launch_convert<float, double>((const c128 *)x, a, n * nc, c->st);
-      launch_coarse_apply<float>(c->cg, c->d32.Qc.p, a, a + n * nc, S, n, false, c->st);
+      if (c->p.coarse_bf16)
+        launch_coarse_apply_bf16(c->cg, c->QcB.p, a, a + n * nc, S, n, false, c->st);
+      else
+        launch_coarse_apply<float>(c->cg, c->d32.Qc.p, a, a + n * nc, S, n, false, c->st);
       launch_convert<double, float>(a + n * nc, (c128 *)y, n * nc, c->st);
     }
     sync(c);

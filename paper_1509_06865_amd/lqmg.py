@@ -42,7 +42,8 @@ class _Params(C.Structure):
                 ("fgmres_restarts", C.c_int), ("n_init", C.c_int), ("n_setup", C.c_int),
                 ("rqi_block", C.c_int), ("rqi_max_sweeps", C.c_int), ("rqi_solve_tol", C.c_double),
                 ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int), ("rqi_solve_restarts", C.c_int),
-                ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int), ("graphs", C.c_int)]
+                ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int), ("graphs", C.c_int),
+                ("coarse_bf16", C.c_int)]
 
 
 class _SolveStats(C.Structure):
@@ -80,6 +81,7 @@ class MGParams:
     rqi_deflate: int | None = None
     rqi_start_passes: int | None = None
     graphs: int | None = None
+    coarse_bf16: int | None = None
 
     def to_c(self, lib) -> _Params:
         p = _Params()

@@ -135,11 +135,13 @@ def coarse_kernel():
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 3e-6)], ids=["fp64", "fp32"])
-def test_coarse_apply_many_sites(prec, tol, variant, coarse_kernel):
+@pytest.mark.parametrize("prec,tol,bf16", [(0, 1e-12, 0), (1, 3e-6, 0), (1, 1e-2, 1)], ids=["fp64", "fp32", "bf16"])
+def test_coarse_apply_many_sites(prec, tol, bf16, variant, coarse_kernel):
     # 8192 coarse sites, each of the six coarse-apply kernels (one wave per
     # (site, rhs); LDS-staged blocks for 4, 8, 16 rhs per pass, per site or
-    # per (site, chunk of 4 or 8 rhs)), FP64 or FP32; 11 rhs leave a ragged chunk
+    # per (site, chunk of 4 or 8 rhs)), FP64, FP32, or FP32 arithmetic on a
+    # bfloat16 copy of Q_c (entries rounded to 2^-9 relative); 11 rhs leave a
+    # ragged chunk
     coarse_kernel(variant)
     dims, agg = (16, 16, 16, 32), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 31)
@@ -147,7 +149,7 @@ def test_coarse_apply_many_sites(prec, tol, variant, coarse_kernel):
     from paper_1509_06865_amd import MGParams
     c = _ctx(dims, 1)
     c.mg_setup(dev(U), -0.15, agg, dev(lqsynth.gaussian_spinors(4, dims, 32)),
-               MGParams(precision=prec, n_setup=0, n_init=1))
+               MGParams(precision=prec, n_setup=0, n_init=1, coarse_bf16=bf16))
     P = host(c.get_interp())
     ag = M.Aggregation(lat, agg)
     Qc = M.coarse_operator(WilsonOp(U, -0.15, lat), ag, P)
@@ -160,6 +162,8 @@ def test_coarse_apply_many_sites(prec, tol, variant, coarse_kernel):
     y = host(c.coarse_apply(sig, dev(x)))
     ref = np.stack([M.coarse_apply(Qc, ag, x[k], sig[k]) for k in range(nr)])
     assert relmax(y, ref) < tol
+    if bf16:
+        assert relmax(y, ref) > 1e-5          # the bfloat16 operator was the one applied
 
 
 def test_coarse_apply_galerkin_identity_full_blocks():
@@ -372,9 +376,9 @@ def test_coarse_graph_replay_equals_direct_launches(prec):
 # the damped shifts land inside it; with Nv = 8 the multigrid-preconditioned
 # FGMRES does not converge there (the oracle needs > 400 steps at sigma = 0.49),
 # with Nv = 16 it takes ~20.  That case therefore runs with 16 test vectors.
-@pytest.mark.parametrize("name,prec,nv", [("tiny_periodic", 0, 8), ("tiny_periodic", 1, 8),
-                                          ("tiny_antiperiodic", 1, 16)])
-def test_rqi_lowest_eight_match_dense(name, prec, nv):
+@pytest.mark.parametrize("name,prec,nv,bf16", [("tiny_periodic", 0, 8, 0), ("tiny_periodic", 1, 8, 0),
+                                               ("tiny_antiperiodic", 1, 16, 0), ("tiny_periodic", 1, 8, 1)])
+def test_rqi_lowest_eight_match_dense(name, prec, nv, bf16):
     dims, bc, eps, seed, m0 = tiny(name)
     U = lqsynth.gauge_field(dims, eps, seed)
     lat = Lattice(dims, bc)
@@ -382,7 +386,7 @@ def test_rqi_lowest_eight_match_dense(name, prec, nv):
     c = _ctx(dims, bc)
     c.mg_setup(dev(U), m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(nv, dims, 102)),
                MGParams(precision=prec, coarse_m=128, coarse_tol=1e-8, coarse_restarts=2, n_setup=4,
-                        rqi_block=4, rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1))
+                        rqi_block=4, rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1, coarse_bf16=bf16))
     n_extra = max(0, 8 + 4 - nv)
     V0 = dev(lqsynth.gaussian_spinors(n_extra, dims, 103)) if n_extra else None
     lam, V, res, info = c.rqi_lowmodes(8, 1e-10, V0=V0)
