@@ -223,8 +223,8 @@ def main():
                     help="kernel class timed live for the roofline object (default: the step's dominant one)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              f"described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the solver over "
+              f"several GPUs (by shift or by lattice) is designed but not built", file=sys.stderr)
         sys.exit(2)
     if args.kernel_only:
         kernel_only(args)
