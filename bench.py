@@ -146,6 +146,47 @@ KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
           "combine": (6, "basis combination k_combine")}
 
 
+def coarse_variants(args):
+    """Time each coarse-apply kernel (0: one wave per (site, field); 1-3: LDS-staged
+    blocks for 4, 8, 16 fields per pass; 4, 5: as 1, 2 per (site, chunk of
+    fields)) with the FP32 coarse operator and with its bfloat16 copy, on the
+    coarse grid of a 16^3 x 32 lattice with 2^4 aggregates and Nv = 24 (8192
+    coarse sites, 48 x 48 blocks), 16 fields, through the library's kernel timer.
+    Prints one JSON line per (storage, kernel)."""
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import (KT_COARSE, Context, MGParams, coarse_variant, kernel_timer_read,
+                                      kernel_timer_start)
+    dims, agg, nv, nf = (16, 16, 16, 32), (2, 2, 2, 2), 24, 16
+    n_sites = int(np.prod([d // a for d, a in zip(dims, agg)]))
+    U = torch.from_numpy(lqsynth.gauge_field(dims, 0.25, 31)).cuda()
+    tv0 = device_gaussian(nv, dims, 32, torch)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    shape = (nf, n_sites, 2 * nv)
+    x = torch.complex(torch.randn(shape, generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn(shape, generator=g, device="cuda", dtype=torch.float64))
+    sig = [0.01 * k for k in range(nf)]
+    for bf16 in (0, 1):
+        ctx = Context(dims, 1)
+        ctx.mg_setup(U, -0.15, agg, tv0, MGParams(precision=1, n_setup=0, n_init=1, coarse_bf16=bf16))
+        for v in range(6):
+            coarse_variant(v)
+            ctx.coarse_apply(sig, x)
+            torch.cuda.synchronize()
+            kernel_timer_start(KT_COARSE)
+            for _ in range(10):
+                ctx.coarse_apply(sig, x)
+            torch.cuda.synchronize()
+            n, ms, by = kernel_timer_read()
+            print(json.dumps({"coarse_storage": "bf16" if bf16 else "fp32", "kernel": v, "coarse_sites": n_sites,
+                              "block": 2 * nv, "fields": nf, "avg_launch_ms": round(ms / n, 4),
+                              "bytes_per_launch": by / n, "algorithmic_GBs": round(by / (ms * 1e-3) / 1e9, 1)}),
+                  flush=True)
+        coarse_variant(-1)
+        del ctx
+
+
 def kernel_only(args):
     """Launch only the kernels of one class on the workload's lattice, plus a
     plain device copy of known size (12 V complex128 read and written), for
@@ -219,6 +260,8 @@ def main():
     ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the roofline kernel class and a reference copy (for counter passes)")
+    ap.add_argument("--coarse-variants", action="store_true",
+                    help="time the six coarse-apply kernels with FP32 and bfloat16 storage (8192 coarse sites)")
     ap.add_argument("--roofline-class", default=DEFAULT_CLASS, choices=sorted(KCLASS) + ["all"],
                     help="kernel class timed live for the roofline object (default: the step's dominant one)")
     args = ap.parse_args()
@@ -226,6 +269,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the solver over "
               f"several GPUs (by shift or by lattice) is designed but not built", file=sys.stderr)
         sys.exit(2)
+    if args.coarse_variants:
+        coarse_variants(args)
+        return
     if args.kernel_only:
         kernel_only(args)
         return
