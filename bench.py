@@ -34,7 +34,7 @@ TRAFFIC = {
                         "source_sha256": "f0bb59517c4b540d91b95fafaa30216e14ebc7f4a23629f88098bc6a7de29de0"},
     # k_coarse_apply<float>, 16 right-hand sides, 256 coarse sites of 40 unknowns
     ("coarse", "medium"): {"bytes_per_launch": 16.17e6,
-                           "source_sha256": "7658face91ec48152544ba819b4b50360e775b344dba1b2c870dd134425df17a"},
+                           "source_sha256": "99ecebd727a242a9cdc02b7d7d6ee5ef944c55ba736c123e8d41bd057266d979"},
 }
 KSOURCES = {"wilson": ["wilson.hip", "lq_dslash.h"], "sap": ["sap.hip", "lq_dslash.h"],
             "restrict": ["transfer.hip"], "prolong": ["transfer.hip"], "coarse": ["coarse.hip"],

@@ -267,9 +267,16 @@ int tune_coarse_apply_q(const CoarseGeom &cg, const QT *Qc, const cplx<T> *x, cp
   if (known >= 0) return known;
   Shifts z{};
   KTimerScope off(KT_COUNT, 0.0);     // never a selected class: untimed
-  hipEvent_t e0, e1;
-  LQ_HIP(hipEventCreate(&e0));
-  LQ_HIP(hipEventCreate(&e1));
+  struct Events {                     // released on every exit, errors included
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  LQ_HIP(hipEventCreate(&ev.a));
+  LQ_HIP(hipEventCreate(&ev.b));
+  const hipEvent_t e0 = ev.a, e1 = ev.b;
   int best = 0;
   float tbest = 1e30f;
   for (int v = 0; v < kCoarseVariants; ++v) {
@@ -282,8 +289,6 @@ int tune_coarse_apply_q(const CoarseGeom &cg, const QT *Qc, const cplx<T> *x, cp
     LQ_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (ms < tbest) { tbest = ms; best = v; }
   }
-  LQ_HIP(hipEventDestroy(e0));
-  LQ_HIP(hipEventDestroy(e1));
   std::lock_guard<std::mutex> lk(g_coarse_mu);
   g_coarse_choice[coarse_key(cg, storage_code<T, QT>(), nrhs)] = best;
   return best;
