@@ -141,8 +141,12 @@ int q_apply_c64(lq_ctx *ctx, const lq_c64 *U, double m0, const lq_c64 *x,
  * n_tv: number Nv of test vectors (2*Nv coarse unknowns per aggregate,
  * 1 <= Nv <= min(32, 6*prod(agg))).  tv0: device [n_tv][12][V] random start
  * vectors (the method draws no random numbers itself).  p: NULL = defaults.
- * Copies U; replaces any previous hierarchy.
- * Errors: LQ_ERR_ARG, LQ_ERR_OOM, LQ_ERR_NUMERIC (locally dependent vectors). */
+ * Copies U; replaces any previous hierarchy.  After an error the context holds
+ * no hierarchy (solve and RQI calls return LQ_ERR_STATE until a setup succeeds).
+ * Start vectors that are linearly dependent on an aggregate are an error; if
+ * the setup's multigrid passes make them so, those aggregates keep their
+ * previous interpolation columns.
+ * Errors: LQ_ERR_ARG, LQ_ERR_OOM, LQ_ERR_NUMERIC (locally dependent start vectors). */
 int mg_setup(lq_ctx *ctx, const lq_c128 *U, double m0, const int agg[4],
              int n_tv, const lq_c128 *tv0, const lq_mg_params *p);
 

@@ -1122,6 +1122,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
              const lq_mg_params *prm) {
   return guard(c, [&] {
     check_ctx(c);
+    c->have = false;                     // a failed setup leaves no usable hierarchy
     if (!U || !agg || !tv0) fail(LQ_ERR_ARG, "mg_setup: NULL pointer");
     int bvol = 1;
     for (int m = 0; m < 4; ++m) {
@@ -1145,7 +1146,6 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
     if (p.coarse_bf16 && p.precision != LQ_PREC_MIXED) fail(LQ_ERR_ARG, "coarse_bf16 needs LQ_PREC_MIXED");
     if (p.coarse_m < 1 || p.fgmres_m < 1 || p.sap_mr < 0 || p.post < 0 || p.pre < 0)
       fail(LQ_ERR_ARG, "bad iteration parameters");
-    c->have = false;
     c->p = p;
     c->m0 = m0;
     c->Nv = n_tv;
@@ -1185,8 +1185,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
         copy<double>(c, W + k0 * V12, tmp, (size_t)nk * V12);
       }
     orthonormalise(c, W, n_tv);
-    rebuild(c, W);
-    c->have = true;
+    rebuild(c, W);                       // dependent start vectors are an error
     for (int it = 0; it < p.n_setup; ++it) {
       for (int k0 = 0; k0 < n_tv; k0 += kMaxRhs) {
         const int nk = std::min(kMaxRhs, n_tv - k0);
@@ -1194,7 +1193,10 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
         copy<double>(c, W + k0 * V12, tmp, (size_t)nk * V12);
       }
       orthonormalise(c, W, n_tv);
-      rebuild(c, W);
+      // vectors the multigrid iteration made locally dependent (a near-null
+      // space thinner than Nv on some aggregate) leave those blocks of P as
+      // they were
+      rebuild(c, W, true);
       if (verbose()) {
         size_t fr = 0, tot = 0;
         (void)hipMemGetInfo(&fr, &tot);
@@ -1204,6 +1206,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
       }
     }
     sync(c);
+    c->have = true;                      // only a setup that completed is usable
     return LQ_OK;
   });
 }

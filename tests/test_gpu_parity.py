@@ -211,7 +211,14 @@ def test_argument_and_state_errors_are_reported():
         c.mg_solve_shifted([0.0] * 17, dev(lqsynth.gaussian_spinors(17, dims, 74)), 1e-6)   # > 16 shifts
     with pytest.raises(LQError):
         c.rqi_lowmodes(4, 1e-10, V0=dev(lqsynth.gaussian_spinors(5, dims, 75)))             # wrong V0 count
-    # empty inputs: no fields, no shifts, no eigenpairs
+    # a failed setup leaves no usable hierarchy: the next solve is a state error
+    c2 = _ctx(dims, bc)
+    c2.mg_setup(U, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(4, dims, 77)), MGParams(n_setup=0))
+    with pytest.raises(LQError):
+        c2.mg_setup(U, m0, (3, 2, 2, 2), x, MGParams(n_setup=0))
+    with pytest.raises(LQError):
+        c2.mg_solve_shifted([0.0], x[:1], 1e-6)
+        # empty inputs: no fields, no shifts, no eigenpairs
     with pytest.raises(LQError):
         c.q_apply(U, m0, x[:0])
     with pytest.raises(LQError):
