@@ -14,6 +14,8 @@ Modules
   mg      aggregation, gamma5-split interpolation P, Galerkin Q_c = P^dag Q P,
           SAP and GMRES smoothers, the two-grid cycle E_2g, adaptive setup
   rqi     Rayleigh quotient iteration with multigrid (Alg. 1), Rayleigh-Ritz
+  lcnn    gauge-equivariant network proposing test vectors and its training loss
+          (not in the paper; the reference for an optional learned setup)
 
 All inner products use numpy's pairwise summation (``np.sum`` over a
 contiguous array), never a running sum.
