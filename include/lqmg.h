@@ -184,6 +184,21 @@ int rqi_lowmodes(lq_ctx *ctx, int n_eig, double tol, double *lambda,
 int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
                       long long n, lq_c128 *out);
 
+/* ---- learned setup: network layer (not part of the paper) ------------------- */
+/* One parallel-transport convolution of the network that proposes multigrid
+ * test vectors:  out[o](x) = sum_{i < c_in} sum_{d in {-1,0,1}^4}
+ * W[o][i][d] T_d(x) phi[i](x + d), where T_d(x) is the product of the links
+ * along the path from x to x + d through the directions x, y, z, t in that
+ * order (U_mu(y) for a step +mu, U_mu(y - mu)^dag for a step -mu, the t
+ * boundary sign for a step across it).  Offsets are numbered
+ * k = sum_mu (d_mu + 1) 3^(3 - mu).  All pointers are device memory in the
+ * canonical layout: U [4][9][V] as for q_apply, phi [c_in][12][V],
+ * W [c_out][c_in][81][4][4] (spin matrices, row-major), out [c_out][12][V].
+ * FP64, asynchronous on the context's stream.  1 <= c_in, c_out <= 64.
+ * Errors: LQ_ERR_ARG. */
+int lq_ptc_forward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
+                   const lq_c128 *W, lq_c128 *out);
+
 /* ---- dense helper ----------------------------------------------------------- */
 /* Eigen-decomposition of the Hermitian part of the n x n matrix A (host,
  * row-major): w[j] ascending, V (host, row-major) holds the orthonormal

@@ -139,4 +139,10 @@ int coarse_force_variant(int v);
 template <typename T>
 void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nrhs, hipStream_t st);
 
+// ---- parallel-transport convolution (ptc.hip) ---------------------------------
+// out[o] = sum_i sum_d W[o][i][d] T_d phi[i](. + d), canonical layout, FP64;
+// phi [cin][12][V], W [cout][cin][81][4][4], out [cout][12][V]
+void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
+                        hipStream_t st);
+
 }  // namespace lq

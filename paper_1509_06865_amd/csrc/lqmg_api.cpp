@@ -1534,6 +1534,18 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
   });
 }
 
+int lq_ptc_forward(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out, const lq_c128 *W,
+                   lq_c128 *out) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !phi || !W || !out || c_in < 1 || c_in > 64 || c_out < 1 || c_out > 64)
+      fail(LQ_ERR_ARG, "lq_ptc_forward: NULL pointer or channel count outside 1..64");
+    launch_ptc_forward(c->gcan, (const c128 *)U, c_in, (const c128 *)phi, c_out, (const c128 *)W, (c128 *)out,
+                       c->st);
+    return LQ_OK;
+  });
+}
+
 int lq_coarse_variant(int v) { return coarse_force_variant(v) == 0 ? LQ_OK : LQ_ERR_ARG; }
 
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V) {

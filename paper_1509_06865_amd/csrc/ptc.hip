@@ -1,0 +1,106 @@
+// Parallel-transport convolution: the layer of the network that proposes
+// multigrid test vectors for the learned setup (not part of the paper).
+//
+//   out[o](x) = sum_i sum_{d in {-1,0,1}^4} W[o][i][d] T_d(x) phi[i](x + d)
+//
+// W[o][i][d] is a 4x4 complex matrix on spin; T_d(x) the 3x3 colour matrix
+// given by the product of the links along the path from x to x + d that steps
+// through the directions 0, 1, 2, 3 in that order: U_mu(y) for a step +mu from
+// y, U_mu(y - mu)^dag for a step -mu, times the boundary sign for a step across
+// the t boundary.  Offsets are numbered k = sum_mu (d_mu + 1) 3^(3 - mu).
+//
+// This is the direct form: one thread per (site, output channel), the path
+// products formed on the fly, FP64.  It is the correctness reference on the
+// device for the GEMM-shaped (MFMA) form the layer takes at scale.
+#include "lq_kernels.h"
+#include "lq_dslash.h"
+
+namespace lq {
+namespace {
+
+constexpr int kPtcOffsets = 81;
+
+__device__ inline void mat3_mul(const c128 A[9], const c128 B[9], c128 C[9]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) C[3 * a + b] = A[3 * a] * B[b] + A[3 * a + 1] * B[3 + b] + A[3 * a + 2] * B[6 + b];
+}
+
+__global__ void __launch_bounds__(256) k_ptc_forward(Geom g, const c128 *__restrict__ U, int cin,
+                                                     const c128 *__restrict__ phi, const c128 *__restrict__ W,
+                                                     c128 *__restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.V) return;
+  const int o = blockIdx.y;
+  const long long V = g.V;
+  c128 acc[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) acc[e] = c128{0, 0};
+  for (int k = 0; k < kPtcOffsets; ++k) {
+    int d[4];
+    int r = k;
+    for (int mu = 3; mu >= 0; --mu) { d[mu] = r % 3 - 1; r /= 3; }
+    // T_d(x) along the path, and the end point x + d
+    c128 T[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) T[e] = c128{(e % 4 == 0) ? 1.0 : 0.0, 0};
+    int pos = x;
+    for (int mu = 0; mu < 4; ++mu) {
+      if (d[mu] == 0) continue;
+      const SiteCoord c = decode(g, pos);
+      float sg;
+      bool in;
+      c128 L[9], P[9];
+      if (d[mu] > 0) {
+        const int nxt = neighbour(g, pos, c, mu, true, &sg, &in);
+        load_link(U, V, mu, pos, L);
+        pos = nxt;
+      } else {
+        const int nxt = neighbour(g, pos, c, mu, false, &sg, &in);
+        c128 M[9];
+        load_link(U, V, mu, nxt, M);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) L[3 * a + b] = conj(M[3 * b + a]);
+        pos = nxt;
+      }
+#pragma unroll
+      for (int e = 0; e < 9; ++e) L[e] = (double)sg * L[e];
+      mat3_mul(T, L, P);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) T[e] = P[e];
+    }
+    for (int i = 0; i < cin; ++i) {
+      c128 p[12], q[12];
+      load_spinor(phi + (long long)i * 12 * V, V, pos, p);
+      // colour: q[s][a] = sum_b T[a][b] p[s][b]
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          q[3 * s + a] = T[3 * a] * p[3 * s] + T[3 * a + 1] * p[3 * s + 1] + T[3 * a + 2] * p[3 * s + 2];
+      // spin: acc[s][a] += sum_t W[o][i][k][s][t] q[t][a]
+      const c128 *w = W + (((long long)o * cin + i) * kPtcOffsets + k) * 16;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const c128 w0 = w[4 * s], w1 = w[4 * s + 1], w2 = w[4 * s + 2], w3 = w[4 * s + 3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[3 * s + a] = acc[3 * s + a] + w0 * q[a] + w1 * q[3 + a] + w2 * q[6 + a] + w3 * q[9 + a];
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 12; ++e) out[((long long)o * 12 + e) * V + x] = acc[e];
+}
+
+}  // namespace
+
+void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_ptc_forward, dim3(blocks_for(g.V, 256), cout), dim3(256), 0, st, g, U, cin, phi, W, out);
+  LQ_HIP(hipGetLastError());
+}
+
+}  // namespace lq

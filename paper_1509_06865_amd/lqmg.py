@@ -23,7 +23,7 @@ SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
-            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant"]
+            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -130,6 +130,7 @@ def load():
         "lq_kernel_timer_read": (i, [C.POINTER(C.c_longlong), dp, dp]),
         "lq_herm_eigh": (i, [i, vp, vp, vp]),
         "lq_coarse_variant": (i, [i]),
+        "lq_ptc_forward": (i, [vp, vp, i, vp, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +197,17 @@ class Context:
         else:
             raise TypeError("x must be complex64 or complex128")
         return y
+
+    def ptc_forward(self, U: torch.Tensor, phi: torch.Tensor, W: torch.Tensor):
+        """One parallel-transport convolution (complex128): phi [c_in, 12, V],
+        W [c_out, c_in, 81, 4, 4] -> [c_out, 12, V]."""
+        c_in, c_out = int(phi.shape[0]), int(W.shape[0])
+        if tuple(W.shape) != (c_out, c_in, 81, 4, 4):
+            raise ValueError("W must be [c_out, c_in, 81, 4, 4]")
+        out = torch.empty((c_out,) + tuple(phi.shape[1:]), dtype=phi.dtype, device=phi.device)
+        self._check(self.lib.lq_ptc_forward(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
+                                            _ptr(out)))
+        return out
 
     # -- multigrid ------------------------------------------------------------------
     def mg_setup(self, U, m0, agg, tv0, params: MGParams | None = None):

@@ -127,6 +127,29 @@ def test_q_apply_full_size_sampled_sites():
     assert relmax(host(y32[0])[:, sites], ref) < 2e-6
 
 
+@pytest.mark.parametrize("t_bc", [-1, 1])
+def test_ptc_layer_matches_oracle(t_bc):
+    # one parallel-transport convolution of the learned setup's network: a
+    # random 3 -> 2 channel layer against the oracle's layer, and the hopping
+    # weights, with which the layer is D (gamma5 of it is q_apply)
+    from oracle import lcnn
+    dims = (4, 2, 4, 6)
+    lat = Lattice(dims, t_bc)
+    U = lqsynth.gauge_field(dims, 0.4, 91)
+    phi = lqsynth.gaussian_spinors(3, dims, 92)
+    rng = np.random.default_rng(93)
+    W = (rng.standard_normal((2, 3, 81, 4, 4)) + 1j * rng.standard_normal((2, 3, 81, 4, 4))) / 30
+    ref = lcnn.forward(lcnn.transports(U, lat), torch.from_numpy(phi), [torch.from_numpy(W)], []).numpy()
+    c = _ctx(dims, t_bc)
+    y = host(c.ptc_forward(dev(U), dev(phi), dev(W)))
+    assert relmax(y, ref) < 1e-13
+    Wd = lcnn.wilson_weights(-0.3).numpy()
+    yd = host(c.ptc_forward(dev(U), dev(phi[:1]), dev(Wd)))
+    q = host(c.q_apply(dev(U), -0.3, dev(phi[:1])))
+    g5 = np.array([1.0] * 6 + [-1.0] * 6)[:, None]
+    assert relmax(g5 * yd[0], q[0]) < 1e-13
+
+
 @pytest.fixture
 def coarse_kernel():
     from paper_1509_06865_amd import coarse_variant
