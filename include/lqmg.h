@@ -198,6 +198,13 @@ int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c1
  * Errors: LQ_ERR_ARG. */
 int lq_ptc_forward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
                    const lq_c128 *W, lq_c128 *out);
+/* The network's nonlinearity between layers (gauge invariant): for channel c
+ * and site x, out[c](x) = phi[c](x) * max(|phi[c](x)| + b[c], 0) / |phi[c](x)|,
+ * |.| the norm over the 12 spin-colour components (out = 0 where phi = 0).
+ * phi, out: device [channels][12][V] (out may equal phi); b: device double
+ * [channels].  Asynchronous on the context's stream.  1 <= channels <= 64.
+ * Errors: LQ_ERR_ARG. */
+int lq_mod_relu(lq_ctx *ctx, int channels, const lq_c128 *phi, const double *b, lq_c128 *out);
 
 /* ---- dense helper ----------------------------------------------------------- */
 /* Eigen-decomposition of the Hermitian part of the n x n matrix A (host,

@@ -1546,6 +1546,16 @@ int lq_ptc_forward(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, in
   });
 }
 
+int lq_mod_relu(lq_ctx *c, int channels, const lq_c128 *phi, const double *b, lq_c128 *out) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!phi || !b || !out || channels < 1 || channels > 64)
+      fail(LQ_ERR_ARG, "lq_mod_relu: NULL pointer or channel count outside 1..64");
+    launch_mod_relu(c->gcan.V, channels, (const c128 *)phi, b, (c128 *)out, c->st);
+    return LQ_OK;
+  });
+}
+
 int lq_coarse_variant(int v) { return coarse_force_variant(v) == 0 ? LQ_OK : LQ_ERR_ARG; }
 
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V) {

@@ -95,7 +95,35 @@ __global__ void __launch_bounds__(256) k_ptc_forward(Geom g, const c128 *__restr
   for (int e = 0; e < 12; ++e) out[((long long)o * 12 + e) * V + x] = acc[e];
 }
 
+// phi -> phi * relu(|phi(x)| + b[c]) / |phi(x)| for channel c at site x, with
+// |phi(x)| the norm over the 12 spin-colour components (0 where it vanishes).
+// One thread per (site, channel); out may be phi.
+__global__ void __launch_bounds__(256) k_mod_relu(int V, const c128 *__restrict__ phi, const double *__restrict__ b,
+                                                  c128 *__restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  const int ch = blockIdx.y;
+  const c128 *p = phi + (long long)ch * 12 * V + x;
+  c128 v[12];
+  double n2 = 0;
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    v[e] = p[(long long)e * V];
+    n2 += v[e].re * v[e].re + v[e].im * v[e].im;
+  }
+  const double n = sqrt(n2);
+  const double scale = (n > 0) ? fmax(n + b[ch], 0.0) / n : 0.0;
+  c128 *q = out + (long long)ch * 12 * V + x;
+#pragma unroll
+  for (int e = 0; e < 12; ++e) q[(long long)e * V] = scale * v[e];
+}
+
 }  // namespace
+
+void launch_mod_relu(int V, int channels, const c128 *phi, const double *b, c128 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mod_relu, dim3(blocks_for(V, 256), channels), dim3(256), 0, st, V, phi, b, out);
+  LQ_HIP(hipGetLastError());
+}
 
 void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
                         hipStream_t st) {

@@ -23,7 +23,7 @@ SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
-            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward"]
+            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -131,6 +131,7 @@ def load():
         "lq_herm_eigh": (i, [i, vp, vp, vp]),
         "lq_coarse_variant": (i, [i]),
         "lq_ptc_forward": (i, [vp, vp, i, vp, i, vp, vp]),
+        "lq_mod_relu": (i, [vp, i, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -208,6 +209,23 @@ class Context:
         self._check(self.lib.lq_ptc_forward(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
                                             _ptr(out)))
         return out
+
+    def mod_relu(self, phi: torch.Tensor, b: torch.Tensor):
+        """The network's nonlinearity: phi [C, 12, V] complex128, b [C] float64 (device)."""
+        out = torch.empty_like(phi)
+        bb = b.to(device=phi.device, dtype=torch.float64).contiguous()
+        self._check(self.lib.lq_mod_relu(self.h, int(phi.shape[0]), _ptr(phi), _ptr(bb), _ptr(out)))
+        return out
+
+    def lcnn_forward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases):
+        """The learned setup's network on the device: the layers and the
+        nonlinearities in turn (each a library call)."""
+        phi = phi0
+        for layer, W in enumerate(weights):
+            phi = self.ptc_forward(U, phi, W)
+            if layer < len(weights) - 1:
+                phi = self.mod_relu(phi, biases[layer])
+        return phi
 
     # -- multigrid ------------------------------------------------------------------
     def mg_setup(self, U, m0, agg, tv0, params: MGParams | None = None):

@@ -150,6 +150,27 @@ def test_ptc_layer_matches_oracle(t_bc):
     assert relmax(g5 * yd[0], q[0]) < 1e-13
 
 
+def test_learned_setup_network_forward_matches_oracle():
+    # three layers 3 -> 4 -> 4 -> 2 with the nonlinearity between them (biases
+    # that cut some sites to zero), device chain against the oracle's forward
+    from oracle import lcnn
+    dims = (4, 2, 4, 6)
+    lat = Lattice(dims, -1)
+    U = lqsynth.gauge_field(dims, 0.4, 95)
+    phi = lqsynth.gaussian_spinors(3, dims, 96)
+    rng = np.random.default_rng(97)
+    chans = (3, 4, 4, 2)
+    Ws = [(rng.standard_normal((co, ci, 81, 4, 4)) + 1j * rng.standard_normal((co, ci, 81, 4, 4))) / (10 * ci)
+          for ci, co in zip(chans[:-1], chans[1:])]
+    bs = [-0.5 * rng.random(co) for co in chans[1:-1]]
+    ref = lcnn.forward(lcnn.transports(U, lat), torch.from_numpy(phi), [torch.from_numpy(w) for w in Ws],
+                       [torch.from_numpy(b) for b in bs]).numpy()
+    c = _ctx(dims, -1)
+    y = host(c.lcnn_forward(dev(U), dev(phi), [dev(w) for w in Ws],
+                            [torch.from_numpy(b).cuda() for b in bs]))
+    assert relmax(y, ref) < 1e-12
+
+
 @pytest.fixture
 def coarse_kernel():
     from paper_1509_06865_amd import coarse_variant
