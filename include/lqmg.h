@@ -198,6 +198,14 @@ int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c1
  * Errors: LQ_ERR_ARG. */
 int lq_ptc_forward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
                    const lq_c128 *W, lq_c128 *out);
+/* Gradients through lq_ptc_forward for a real loss L: given g_out =
+ * dL/dRe(out) + i dL/dIm(out) (device [c_out][12][V]), writes g_in (device
+ * [c_in][12][V]) and g_W (device [c_out][c_in][81][4][4]) of the same form for
+ * phi and W; either output may be NULL.  g_in is the adjoint convolution, g_W
+ * sums over the sites in a fixed order.  FP64, asynchronous on the context's
+ * stream.  Errors: LQ_ERR_ARG. */
+int lq_ptc_backward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
+                    const lq_c128 *W, const lq_c128 *g_out, lq_c128 *g_in, lq_c128 *g_W);
 /* The network's nonlinearity between layers (gauge invariant): for channel c
  * and site x, out[c](x) = phi[c](x) * max(|phi[c](x)| + b[c], 0) / |phi[c](x)|,
  * |.| the norm over the 12 spin-colour components (out = 0 where phi = 0).

@@ -144,6 +144,10 @@ void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nr
 // phi [cin][12][V], W [cout][cin][81][4][4], out [cout][12][V]
 void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
                         hipStream_t st);
+// gradients of a real loss through the layer (g = dL/dRe out + i dL/dIm out): gin [cin][12][V]
+// and gW [cout][cin][81][4][4] in the same form; either may be null
+void launch_ptc_backward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
+                         const c128 *gout, c128 *gin, c128 *gW, hipStream_t st);
 // out[c] = phi[c] * relu(|phi[c](x)| + b[c]) / |phi[c](x)| (spin-colour norm per site); out may be phi
 void launch_mod_relu(int V, int channels, const c128 *phi, const double *b, c128 *out, hipStream_t st);
 

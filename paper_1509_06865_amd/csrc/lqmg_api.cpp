@@ -1546,6 +1546,18 @@ int lq_ptc_forward(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, in
   });
 }
 
+int lq_ptc_backward(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out, const lq_c128 *W,
+                    const lq_c128 *g_out, lq_c128 *g_in, lq_c128 *g_W) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !phi || !W || !g_out || c_in < 1 || c_in > 64 || c_out < 1 || c_out > 64)
+      fail(LQ_ERR_ARG, "lq_ptc_backward: NULL pointer or channel count outside 1..64");
+    launch_ptc_backward(c->gcan, (const c128 *)U, c_in, (const c128 *)phi, c_out, (const c128 *)W,
+                        (const c128 *)g_out, (c128 *)g_in, (c128 *)g_W, c->st);
+    return LQ_OK;
+  });
+}
+
 int lq_mod_relu(lq_ctx *c, int channels, const lq_c128 *phi, const double *b, lq_c128 *out) {
   return guard(c, [&] {
     check_ctx(c);

@@ -27,6 +27,58 @@ __device__ inline void mat3_mul(const c128 A[9], const c128 B[9], c128 C[9]) {
     for (int b = 0; b < 3; ++b) C[3 * a + b] = A[3 * a] * B[b] + A[3 * a + 1] * B[3 + b] + A[3 * a + 2] * B[6 + b];
 }
 
+__device__ inline void offset_of(int k, int d[4]) {
+  for (int mu = 3; mu >= 0; --mu) { d[mu] = k % 3 - 1; k /= 3; }
+}
+
+// T_d(x): the links along the path from x to x + d (directions 0..3 in order,
+// boundary signs included); returns the site x + d.
+__device__ inline int path_transport(const Geom &g, const c128 *__restrict__ U, int x, const int d[4], c128 T[9]) {
+  const long long V = g.V;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) T[e] = c128{(e % 4 == 0) ? 1.0 : 0.0, 0};
+  int pos = x;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (d[mu] == 0) continue;
+    const SiteCoord c = decode(g, pos);
+    float sg;
+    bool in;
+    c128 L[9], P[9];
+    if (d[mu] > 0) {
+      const int nxt = neighbour(g, pos, c, mu, true, &sg, &in);
+      load_link(U, V, mu, pos, L);
+      pos = nxt;
+    } else {
+      const int nxt = neighbour(g, pos, c, mu, false, &sg, &in);
+      c128 M[9];
+      load_link(U, V, mu, nxt, M);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) L[3 * a + b] = conj(M[3 * b + a]);
+      pos = nxt;
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) L[e] = (double)sg * L[e];
+    mat3_mul(T, L, P);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) T[e] = P[e];
+  }
+  return pos;
+}
+
+// the site x - d (the start of the path that ends at y)
+__device__ inline int back_offset(const Geom &g, int y, const int d[4]) {
+  int pos = y;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (d[mu] == 0) continue;
+    float sg;
+    bool in;
+    pos = neighbour(g, pos, decode(g, pos), mu, d[mu] < 0, &sg, &in);
+  }
+  return pos;
+}
+
 __global__ void __launch_bounds__(256) k_ptc_forward(Geom g, const c128 *__restrict__ U, int cin,
                                                      const c128 *__restrict__ phi, const c128 *__restrict__ W,
                                                      c128 *__restrict__ out) {
@@ -39,39 +91,9 @@ __global__ void __launch_bounds__(256) k_ptc_forward(Geom g, const c128 *__restr
   for (int e = 0; e < 12; ++e) acc[e] = c128{0, 0};
   for (int k = 0; k < kPtcOffsets; ++k) {
     int d[4];
-    int r = k;
-    for (int mu = 3; mu >= 0; --mu) { d[mu] = r % 3 - 1; r /= 3; }
-    // T_d(x) along the path, and the end point x + d
+    offset_of(k, d);
     c128 T[9];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) T[e] = c128{(e % 4 == 0) ? 1.0 : 0.0, 0};
-    int pos = x;
-    for (int mu = 0; mu < 4; ++mu) {
-      if (d[mu] == 0) continue;
-      const SiteCoord c = decode(g, pos);
-      float sg;
-      bool in;
-      c128 L[9], P[9];
-      if (d[mu] > 0) {
-        const int nxt = neighbour(g, pos, c, mu, true, &sg, &in);
-        load_link(U, V, mu, pos, L);
-        pos = nxt;
-      } else {
-        const int nxt = neighbour(g, pos, c, mu, false, &sg, &in);
-        c128 M[9];
-        load_link(U, V, mu, nxt, M);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) L[3 * a + b] = conj(M[3 * b + a]);
-        pos = nxt;
-      }
-#pragma unroll
-      for (int e = 0; e < 9; ++e) L[e] = (double)sg * L[e];
-      mat3_mul(T, L, P);
-#pragma unroll
-      for (int e = 0; e < 9; ++e) T[e] = P[e];
-    }
+    const int pos = path_transport(g, U, x, d, T);       // T_d(x) and x + d
     for (int i = 0; i < cin; ++i) {
       c128 p[12], q[12];
       load_spinor(phi + (long long)i * 12 * V, V, pos, p);
@@ -93,6 +115,106 @@ __global__ void __launch_bounds__(256) k_ptc_forward(Geom g, const c128 *__restr
   }
 #pragma unroll
   for (int e = 0; e < 12; ++e) out[((long long)o * 12 + e) * V + x] = acc[e];
+}
+
+// Gradients, for a real loss L and g = dL/dRe(out) + i dL/dIm(out) (so that
+// dL = Re sum conj(g) d(out)); the results have the same form for phi and W.
+// Input gradient, one thread per (site y, input channel i):
+//   g_in[i](y) = sum_o sum_d W[o][i][d]^dag T_d(y - d)^dag g[o](y - d).
+__global__ void __launch_bounds__(256) k_ptc_grad_input(Geom g, const c128 *__restrict__ U, int cout,
+                                                        const c128 *__restrict__ gout, int cin,
+                                                        const c128 *__restrict__ W, c128 *__restrict__ gin) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= g.V) return;
+  const int i = blockIdx.y;
+  const long long V = g.V;
+  c128 acc[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) acc[e] = c128{0, 0};
+  for (int k = 0; k < kPtcOffsets; ++k) {
+    int d[4];
+    offset_of(k, d);
+    const int x = back_offset(g, y, d);
+    c128 T[9];
+    (void)path_transport(g, U, x, d, T);              // ends at y
+    for (int o = 0; o < cout; ++o) {
+      c128 p[12], q[12];
+      load_spinor(gout + (long long)o * 12 * V, V, x, p);
+      // colour: q[s][a] = sum_b conj(T[b][a]) p[s][b]
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          q[3 * s + a] = cmul_conj(T[a], p[3 * s]) + cmul_conj(T[3 + a], p[3 * s + 1]) + cmul_conj(T[6 + a], p[3 * s + 2]);
+      // spin: acc[t][a] += sum_s conj(W[s][t]) q[s][a]
+      const c128 *w = W + (((long long)o * cin + i) * kPtcOffsets + k) * 16;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const c128 w0 = w[t], w1 = w[4 + t], w2 = w[8 + t], w3 = w[12 + t];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          acc[3 * t + a] = acc[3 * t + a] + cmul_conj(w0, q[a]) + cmul_conj(w1, q[3 + a]) + cmul_conj(w2, q[6 + a]) +
+                           cmul_conj(w3, q[9 + a]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 12; ++e) gin[((long long)i * 12 + e) * V + y] = acc[e];
+}
+
+// Weight gradient, one workgroup per (o, i, d), sites summed in a fixed order:
+//   g_W[o][i][d][s][t] = sum_x sum_a g[o](x)[s][a] conj((T_d(x) phi[i](x + d))[t][a]).
+__global__ void __launch_bounds__(256) k_ptc_grad_weight(Geom g, const c128 *__restrict__ U, int cin,
+                                                         const c128 *__restrict__ phi, int cout,
+                                                         const c128 *__restrict__ gout, c128 *__restrict__ gW) {
+  __shared__ double red[4][32];
+  const int k = blockIdx.x % kPtcOffsets;
+  const int oi = blockIdx.x / kPtcOffsets;
+  const int i = oi % cin, o = oi / cin;
+  const long long V = g.V;
+  int d[4];
+  offset_of(k, d);
+  double pr[16], pi[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) { pr[e] = 0; pi[e] = 0; }
+  for (int x = threadIdx.x; x < g.V; x += blockDim.x) {
+    c128 T[9], p[12], tp[12], gg[12];
+    const int pos = path_transport(g, U, x, d, T);
+    load_spinor(phi + (long long)i * 12 * V, V, pos, p);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        tp[3 * t + a] = T[3 * a] * p[3 * t] + T[3 * a + 1] * p[3 * t + 1] + T[3 * a + 2] * p[3 * t + 2];
+    load_spinor(gout + (long long)o * 12 * V, V, x, gg);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        c128 v = c128{0, 0};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v = v + cmul_conj(tp[3 * t + a], gg[3 * s + a]);   // gg * conj(tp)
+        pr[4 * s + t] += v.re;
+        pi[4 * s + t] += v.im;
+      }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    double re = pr[e], im = pi[e];
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) { red[wave][2 * e] = re; red[wave][2 * e + 1] = im; }
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int e = threadIdx.x;
+    double re = 0, im = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { re += red[w][2 * e]; im += red[w][2 * e + 1]; }
+    gW[(long long)blockIdx.x * 16 + e] = c128{re, im};
+  }
 }
 
 // phi -> phi * relu(|phi(x)| + b[c]) / |phi(x)| for channel c at site x, with
@@ -123,6 +245,20 @@ __global__ void __launch_bounds__(256) k_mod_relu(int V, const c128 *__restrict_
 void launch_mod_relu(int V, int channels, const c128 *phi, const double *b, c128 *out, hipStream_t st) {
   hipLaunchKernelGGL(k_mod_relu, dim3(blocks_for(V, 256), channels), dim3(256), 0, st, V, phi, b, out);
   LQ_HIP(hipGetLastError());
+}
+
+void launch_ptc_backward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
+                         const c128 *gout, c128 *gin, c128 *gW, hipStream_t st) {
+  if (gin) {
+    hipLaunchKernelGGL(k_ptc_grad_input, dim3(blocks_for(g.V, 256), cin), dim3(256), 0, st, g, U, cout, gout, cin, W,
+                       gin);
+    LQ_HIP(hipGetLastError());
+  }
+  if (gW) {
+    hipLaunchKernelGGL(k_ptc_grad_weight, dim3(cout * cin * kPtcOffsets), dim3(256), 0, st, g, U, cin, phi, cout,
+                       gout, gW);
+    LQ_HIP(hipGetLastError());
+  }
 }
 
 void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,

@@ -23,7 +23,7 @@ SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
-            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu"]
+            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -132,6 +132,7 @@ def load():
         "lq_coarse_variant": (i, [i]),
         "lq_ptc_forward": (i, [vp, vp, i, vp, i, vp, vp]),
         "lq_mod_relu": (i, [vp, i, vp, vp, vp]),
+        "lq_ptc_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -209,6 +210,16 @@ class Context:
         self._check(self.lib.lq_ptc_forward(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
                                             _ptr(out)))
         return out
+
+    def ptc_backward(self, U: torch.Tensor, phi: torch.Tensor, W: torch.Tensor, g_out: torch.Tensor):
+        """Gradients (same form as g_out = dL/dRe out + i dL/dIm out) of a real
+        loss with respect to phi and W through one layer."""
+        c_in, c_out = int(phi.shape[0]), int(W.shape[0])
+        g_in = torch.empty_like(phi)
+        g_W = torch.empty_like(W)
+        self._check(self.lib.lq_ptc_backward(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
+                                             _ptr(g_out.contiguous()), _ptr(g_in), _ptr(g_W)))
+        return g_in, g_W
 
     def mod_relu(self, phi: torch.Tensor, b: torch.Tensor):
         """The network's nonlinearity: phi [C, 12, V] complex128, b [C] float64 (device)."""

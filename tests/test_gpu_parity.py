@@ -150,6 +150,30 @@ def test_ptc_layer_matches_oracle(t_bc):
     assert relmax(g5 * yd[0], q[0]) < 1e-13
 
 
+@pytest.mark.parametrize("t_bc", [-1, 1])
+def test_ptc_layer_gradients_match_oracle_autograd(t_bc):
+    # the layer's input and weight gradients for L = Re sum conj(G) out against
+    # the oracle's autograd (the oracle's gradients are pinned by finite
+    # differences on the CPU)
+    from oracle import lcnn
+    dims = (4, 2, 4, 6)
+    lat = Lattice(dims, t_bc)
+    U = lqsynth.gauge_field(dims, 0.4, 101)
+    phi = lqsynth.gaussian_spinors(3, dims, 102)
+    rng = np.random.default_rng(103)
+    W = (rng.standard_normal((2, 3, 81, 4, 4)) + 1j * rng.standard_normal((2, 3, 81, 4, 4))) / 30
+    G = lqsynth.gaussian_spinors(2, dims, 104)
+    phi_t = torch.from_numpy(phi).requires_grad_(True)
+    W_t = torch.from_numpy(W).requires_grad_(True)
+    out = lcnn.forward(lcnn.transports(U, lat), phi_t, [W_t], [])
+    L = torch.real((torch.from_numpy(G).conj() * out).sum())
+    gphi, gW = torch.autograd.grad(L, [phi_t, W_t])
+    c = _ctx(dims, t_bc)
+    d_in, d_W = c.ptc_backward(dev(U), dev(phi), dev(W), dev(G))
+    assert relmax(host(d_in), gphi.numpy()) < 1e-12
+    assert relmax(host(d_W), gW.numpy()) < 1e-12
+
+
 def test_learned_setup_network_forward_matches_oracle():
     # three layers 3 -> 4 -> 4 -> 2 with the nonlinearity between them (biases
     # that cut some sites to zero), device chain against the oracle's forward
