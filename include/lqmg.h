@@ -213,6 +213,13 @@ int lq_ptc_backward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi,
  * [channels].  Asynchronous on the context's stream.  1 <= channels <= 64.
  * Errors: LQ_ERR_ARG. */
 int lq_mod_relu(lq_ctx *ctx, int channels, const lq_c128 *phi, const double *b, lq_c128 *out);
+/* Gradients through lq_mod_relu for a real loss: from g_out (device
+ * [channels][12][V], form as for lq_ptc_backward) writes g_phi (device, same
+ * shape) and g_b (device double [channels], summed over the sites in a fixed
+ * order).  Uses a context-owned scratch of channels * V doubles.  Errors:
+ * LQ_ERR_ARG, LQ_ERR_OOM. */
+int lq_mod_relu_backward(lq_ctx *ctx, int channels, const lq_c128 *phi, const double *b,
+                         const lq_c128 *g_out, lq_c128 *g_phi, double *g_b);
 
 /* ---- dense helper ----------------------------------------------------------- */
 /* Eigen-decomposition of the Hermitian part of the n x n matrix A (host,

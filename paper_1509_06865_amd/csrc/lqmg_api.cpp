@@ -156,6 +156,7 @@ struct lq_ctx {
   DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
   DevBuf<double> coarse_sig;        // shifts of the current coarse solve [kMaxRhs]
   DevBuf<bf16c> QcB;                // the FP32 Q_c in bfloat16 (coarse_bf16)
+  DevBuf<double> net_scratch;       // per-site partial sums of the network's bias gradients
   int coarse_iters = 0;
   // captured coarse-GMRES chunks, keyed by shape, step range and every pointer
   // they use; cap_st is the private stream they are captured on
@@ -1564,6 +1565,19 @@ int lq_mod_relu(lq_ctx *c, int channels, const lq_c128 *phi, const double *b, lq
     if (!phi || !b || !out || channels < 1 || channels > 64)
       fail(LQ_ERR_ARG, "lq_mod_relu: NULL pointer or channel count outside 1..64");
     launch_mod_relu(c->gcan.V, channels, (const c128 *)phi, b, (c128 *)out, c->st);
+    return LQ_OK;
+  });
+}
+
+int lq_mod_relu_backward(lq_ctx *c, int channels, const lq_c128 *phi, const double *b, const lq_c128 *g_out,
+                         lq_c128 *g_phi, double *g_b) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!phi || !b || !g_out || !g_phi || !g_b || channels < 1 || channels > 64)
+      fail(LQ_ERR_ARG, "lq_mod_relu_backward: NULL pointer or channel count outside 1..64");
+    double *scr = c->net_scratch.get((size_t)channels * c->gcan.V);
+    launch_mod_relu_backward(c->gcan.V, channels, (const c128 *)phi, b, (const c128 *)g_out, (c128 *)g_phi, g_b, scr,
+                             c->st);
     return LQ_OK;
   });
 }

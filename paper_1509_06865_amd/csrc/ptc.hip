@@ -240,7 +240,62 @@ __global__ void __launch_bounds__(256) k_mod_relu(int V, const c128 *__restrict_
   for (int e = 0; e < 12; ++e) q[(long long)e * V] = scale * v[e];
 }
 
+// Gradients through the nonlinearity (same convention as the layer's): with
+// n = |phi(x)| and s = relu(n + b) / n, where n + b > 0
+//   g_phi = s g - (b / n^3) Re<g, phi> phi,   contrib(x) = Re<g, phi> / n,
+// and 0 elsewhere; g_b[c] = sum_x contrib(x) (k_sum_rows).
+__global__ void __launch_bounds__(256) k_mod_relu_grad(int V, const c128 *__restrict__ phi,
+                                                       const double *__restrict__ b, const c128 *__restrict__ gout,
+                                                       c128 *__restrict__ gphi, double *__restrict__ contrib) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  const int ch = blockIdx.y;
+  const long long base = (long long)ch * 12 * V + x;
+  c128 v[12], gg[12];
+  double n2 = 0, gp = 0;                               // |phi|^2, Re<g, phi>
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    v[e] = phi[base + (long long)e * V];
+    gg[e] = gout[base + (long long)e * V];
+    n2 += v[e].re * v[e].re + v[e].im * v[e].im;
+    gp += gg[e].re * v[e].re + gg[e].im * v[e].im;
+  }
+  const double n = sqrt(n2);
+  const bool on = n > 0 && n + b[ch] > 0;
+  const double sc = on ? (n + b[ch]) / n : 0.0;
+  const double cphi = on ? -b[ch] * gp / (n2 * n) : 0.0;
+#pragma unroll
+  for (int e = 0; e < 12; ++e) gphi[base + (long long)e * V] = sc * gg[e] + cphi * v[e];
+  contrib[(long long)ch * V + x] = on ? gp / n : 0.0;
+}
+
+// out[r] = sum_x a[r][x], one workgroup per row, fixed order (strided
+// partial sums, then a shuffle tree and the waves in order).
+__global__ void __launch_bounds__(256) k_sum_rows(int V, const double *__restrict__ a, double *__restrict__ out) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  double v = 0;
+  for (int x = threadIdx.x; x < V; x += blockDim.x) v += a[(long long)r * V + x];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    out[r] = t;
+  }
+}
+
 }  // namespace
+
+void launch_mod_relu_backward(int V, int channels, const c128 *phi, const double *b, const c128 *gout, c128 *gphi,
+                              double *gb, double *scratch, hipStream_t st) {
+  hipLaunchKernelGGL(k_mod_relu_grad, dim3(blocks_for(V, 256), channels), dim3(256), 0, st, V, phi, b, gout, gphi,
+                     scratch);
+  LQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3(channels), dim3(256), 0, st, V, scratch, gb);
+  LQ_HIP(hipGetLastError());
+}
 
 void launch_mod_relu(int V, int channels, const c128 *phi, const double *b, c128 *out, hipStream_t st) {
   hipLaunchKernelGGL(k_mod_relu, dim3(blocks_for(V, 256), channels), dim3(256), 0, st, V, phi, b, out);

@@ -23,7 +23,8 @@ SMOOTH_SAP, SMOOTH_GMRES = 0, 1
 EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_apply", "q_apply_c64",
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
-            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward"]
+            "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
+            "lq_mod_relu_backward"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -133,6 +134,7 @@ def load():
         "lq_ptc_forward": (i, [vp, vp, i, vp, i, vp, vp]),
         "lq_mod_relu": (i, [vp, i, vp, vp, vp]),
         "lq_ptc_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp]),
+        "lq_mod_relu_backward": (i, [vp, i, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -227,6 +229,35 @@ class Context:
         bb = b.to(device=phi.device, dtype=torch.float64).contiguous()
         self._check(self.lib.lq_mod_relu(self.h, int(phi.shape[0]), _ptr(phi), _ptr(bb), _ptr(out)))
         return out
+
+    def mod_relu_backward(self, phi: torch.Tensor, b: torch.Tensor, g_out: torch.Tensor):
+        """Gradients through the nonlinearity: (g_phi, g_b)."""
+        bb = b.to(device=phi.device, dtype=torch.float64).contiguous()
+        g_phi = torch.empty_like(phi)
+        g_b = torch.empty_like(bb)
+        self._check(self.lib.lq_mod_relu_backward(self.h, int(phi.shape[0]), _ptr(phi), _ptr(bb),
+                                                  _ptr(g_out.contiguous()), _ptr(g_phi), _ptr(g_b)))
+        return g_phi, g_b
+
+    def lcnn_backward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases, g_out: torch.Tensor):
+        """Gradients of a real loss with respect to every weight and bias of the
+        network, given g_out for its output: the forward is rerun to keep each
+        layer's input, then the library's backward calls run in reverse order."""
+        inputs, pre = [], []
+        phi = phi0
+        for layer, W in enumerate(weights):
+            inputs.append(phi)
+            phi = self.ptc_forward(U, phi, W)
+            if layer < len(weights) - 1:
+                pre.append(phi)
+                phi = self.mod_relu(phi, biases[layer])
+        g = g_out
+        gW, gb = [None] * len(weights), [None] * len(biases)
+        for layer in range(len(weights) - 1, -1, -1):
+            if layer < len(weights) - 1:
+                g, gb[layer] = self.mod_relu_backward(pre[layer], biases[layer], g)
+            g, gW[layer] = self.ptc_backward(U, inputs[layer], weights[layer], g)
+        return gW, gb
 
     def lcnn_forward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases):
         """The learned setup's network on the device: the layers and the

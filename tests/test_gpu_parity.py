@@ -174,6 +174,36 @@ def test_ptc_layer_gradients_match_oracle_autograd(t_bc):
     assert relmax(host(d_W), gW.numpy()) < 1e-12
 
 
+def test_learned_setup_network_gradients_match_oracle_autograd():
+    # backpropagation through three layers and two nonlinearities on the
+    # device (the library's backward calls in reverse order) against autograd
+    # on the oracle's network, for L = Re sum conj(G) output
+    from oracle import lcnn
+    dims = (4, 2, 4, 6)
+    lat = Lattice(dims, -1)
+    U = lqsynth.gauge_field(dims, 0.4, 111)
+    phi = lqsynth.gaussian_spinors(3, dims, 112)
+    rng = np.random.default_rng(113)
+    chans = (3, 4, 4, 2)
+    Ws = [(rng.standard_normal((co, ci, 81, 4, 4)) + 1j * rng.standard_normal((co, ci, 81, 4, 4))) / (10 * ci)
+          for ci, co in zip(chans[:-1], chans[1:])]
+    bs = [-0.5 * rng.random(co) for co in chans[1:-1]]
+    G = lqsynth.gaussian_spinors(2, dims, 114)
+    Wt = [torch.from_numpy(w).requires_grad_(True) for w in Ws]
+    bt = [torch.from_numpy(b).requires_grad_(True) for b in bs]
+    out = lcnn.forward(lcnn.transports(U, lat), torch.from_numpy(phi), Wt, bt)
+    L = torch.real((torch.from_numpy(G).conj() * out).sum())
+    grads = torch.autograd.grad(L, Wt + bt)
+    c = _ctx(dims, -1)
+    gW, gb = c.lcnn_backward(dev(U), dev(phi), [dev(w) for w in Ws], [torch.from_numpy(b).cuda() for b in bs],
+                             dev(G))
+    for k in range(3):
+        assert relmax(host(gW[k]), grads[k].numpy()) < 1e-11, k
+    for k in range(2):
+        ref = grads[3 + k].numpy()
+        assert np.abs(gb[k].cpu().numpy() - ref).max() < 1e-11 * max(np.abs(ref).max(), 1.0), k
+
+
 def test_learned_setup_network_forward_matches_oracle():
     # three layers 3 -> 4 -> 4 -> 2 with the nonlinearity between them (biases
     # that cut some sites to zero), device chain against the oracle's forward
