@@ -221,6 +221,18 @@ int lq_mod_relu(lq_ctx *ctx, int channels, const lq_c128 *phi, const double *b, 
 int lq_mod_relu_backward(lq_ctx *ctx, int channels, const lq_c128 *phi, const double *b,
                          const lq_c128 *g_out, lq_c128 *g_phi, double *g_b);
 
+/* Training loss of the network's outputs: for each aggregate (extents agg,
+ * host int[4], dividing the lattice) and gamma5 half, the part of the targets
+ * u that the span of the outputs X does not represent,
+ *   loss = (1/K) sum_k sum_{A,h} || (1 - Pi_{A,h}) u_k ||^2,
+ * and (if g_X is not NULL) its gradient with respect to X in the form of
+ * lq_ptc_backward.  X: device [n_out][12][V], u: device [K][12][V] (canonical
+ * layout), 1 <= n_out, K <= 32, n_out <= 6 * prod(agg).  loss: host double.
+ * Synchronous.  Errors: LQ_ERR_ARG; LQ_ERR_NUMERIC if the outputs are
+ * linearly dependent on an aggregate half. */
+int lq_proj_loss(lq_ctx *ctx, const int agg[4], int n_out, const lq_c128 *X, int K, const lq_c128 *u,
+                 double *loss, lq_c128 *g_X);
+
 /* ---- dense helper ----------------------------------------------------------- */
 /* Eigen-decomposition of the Hermitian part of the n x n matrix A (host,
  * row-major): w[j] ascending, V (host, row-major) holds the orthonormal

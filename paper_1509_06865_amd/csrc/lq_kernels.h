@@ -150,6 +150,11 @@ void launch_ptc_backward(const Geom &g, const c128 *U, int cin, const c128 *phi,
                          const c128 *gout, c128 *gin, c128 *gW, hipStream_t st);
 // out[c] = phi[c] * relu(|phi[c](x)| + b[c]) / |phi[c](x)| (spin-colour norm per site); out may be phi
 void launch_mod_relu(int V, int channels, const c128 *phi, const double *b, c128 *out, hipStream_t st);
+// training loss of outputs X [nout][12][V] for targets u [K][12][V] over aggregates of extents
+// agg (canonical layout): part [2 * blocks] per-block values, *loss (device) their sum,
+// gX (nullable) the gradient; nout, K <= 32; *status raised if the outputs are dependent
+void launch_proj_loss(const int L[4], const int agg[4], int nout, const c128 *X, int K, const c128 *u, double *part,
+                      double *loss, c128 *gX, int *status, hipStream_t st);
 // gradients through it: gphi [channels][12][V], gb [channels]; scratch: channels * V doubles
 void launch_mod_relu_backward(int V, int channels, const c128 *phi, const double *b, const c128 *gout, c128 *gphi,
                               double *gb, double *scratch, hipStream_t st);

@@ -1582,6 +1582,35 @@ int lq_mod_relu_backward(lq_ctx *c, int channels, const lq_c128 *phi, const doub
   });
 }
 
+int lq_proj_loss(lq_ctx *c, const int agg[4], int n_out, const lq_c128 *X, int K, const lq_c128 *u, double *loss,
+                 lq_c128 *g_X) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!agg || !X || !u || !loss || n_out < 1 || n_out > 32 || K < 1 || K > 32)
+      fail(LQ_ERR_ARG, "lq_proj_loss: NULL pointer or n_out / K outside 1..32");
+    int bvol = 1, nblk = 1;
+    for (int m = 0; m < 4; ++m) {
+      if (agg[m] < 1 || c->L[m] % agg[m]) fail(LQ_ERR_ARG, "lq_proj_loss: aggregate extent does not divide the lattice");
+      bvol *= agg[m];
+      nblk *= c->L[m] / agg[m];
+    }
+    if (n_out > 6 * bvol) fail(LQ_ERR_ARG, "lq_proj_loss: more outputs than rows of an aggregate half");
+    double *part = c->net_scratch.get((size_t)2 * nblk + 1);
+    int *st = c->status.get(1);
+    LQ_HIP(hipMemsetAsync(st, 0, sizeof(int), c->st));
+    launch_proj_loss(c->L, agg, n_out, (const c128 *)X, K, (const c128 *)u, part, part + 2 * nblk, (c128 *)g_X, st,
+                     c->st);
+    double h_loss = 0;
+    int h_st = 0;
+    LQ_HIP(hipMemcpyAsync(&h_loss, part + 2 * nblk, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    LQ_HIP(hipMemcpyAsync(&h_st, st, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    if (h_st) fail(LQ_ERR_NUMERIC, "lq_proj_loss: outputs linearly dependent on an aggregate half");
+    *loss = h_loss;
+    return LQ_OK;
+  });
+}
+
 int lq_coarse_variant(int v) { return coarse_force_variant(v) == 0 ? LQ_OK : LQ_ERR_ARG; }
 
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V) {

@@ -286,7 +286,133 @@ __global__ void __launch_bounds__(256) k_sum_rows(int V, const double *__restric
   }
 }
 
+// Training loss of the network's outputs X ([n_out][12][V]) for targets u
+// ([K][12][V]), canonical layout: for each aggregate A (extents agg) and gamma5
+// half h, with M the (6|A|) x n_out rows of X and B those of u,
+//   coef = (M^dag M)^-1 M^dag B,  R = B - M coef,
+//   loss part = sum |R|^2 / K,  gradient rows = -(2/K) R coef^dag
+// (the gradient in the same form as the layer's).  One workgroup per (A, h);
+// G = M^dag M and C = M^dag B accumulate over the rows, thread 0 solves with
+// Cholesky in LDS.  A non-positive pivot (outputs dependent on the block)
+// raises *status.
+constexpr int kProjMax = 32;
+
+__device__ inline int proj_site(const int L[4], const int agg[4], int blk, int loc) {
+  int x[4];
+  for (int m = 0; m < 4; ++m) {
+    const int nb = L[m] / agg[m];
+    const int a = blk % nb, l = loc % agg[m];
+    blk /= nb;
+    loc /= agg[m];
+    x[m] = a * agg[m] + l;
+  }
+  return x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3]));
+}
+
+struct ProjGeom { int L[4]; int agg[4]; int bvol; int V; };
+
+__global__ void __launch_bounds__(256) k_proj_loss(ProjGeom pg, int nout, const c128 *__restrict__ X, int K,
+                                                   const c128 *__restrict__ u, double *__restrict__ part,
+                                                   c128 *__restrict__ gX, int *__restrict__ status) {
+  __shared__ c128 G[kProjMax][kProjMax];
+  __shared__ c128 C[kProjMax][kProjMax];
+  __shared__ double red[4];
+  __shared__ int bad;
+  const int blk = blockIdx.x >> 1, h = blockIdx.x & 1;
+  const int rows = 6 * pg.bvol;
+  const long long V = pg.V;
+  if (threadIdx.x == 0) bad = 0;
+  // row r: component 6h + r / bvol at the site of local index r % bvol
+  auto at = [&](const c128 *F, int col, int r) -> c128 {
+    const int comp = 6 * h + r / pg.bvol, site = proj_site(pg.L, pg.agg, blk, r % pg.bvol);
+    return F[((long long)col * 12 + comp) * V + site];
+  };
+  for (int e = threadIdx.x; e < nout * nout + nout * K; e += blockDim.x) {
+    const bool isG = e < nout * nout;
+    const int p = isG ? e / nout : (e - nout * nout) / K;
+    const int q = isG ? e % nout : (e - nout * nout) % K;
+    c128 acc = c128{0, 0};
+    for (int r = 0; r < rows; ++r) acc = acc + cmul_conj(at(X, p, r), isG ? at(X, q, r) : at(u, q, r));
+    if (isG) G[p][q] = acc; else C[p][q] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // G = L L^dag in place (lower triangle), then coef = G^-1 C into C
+    for (int j = 0; j < nout; ++j) {
+      double dj = G[j][j].re;
+      for (int k = 0; k < j; ++k) dj -= G[j][k].re * G[j][k].re + G[j][k].im * G[j][k].im;
+      if (!(dj > 0)) { bad = 1; dj = 1.0; }
+      const double ljj = sqrt(dj);
+      G[j][j] = c128{ljj, 0};
+      for (int i = j + 1; i < nout; ++i) {
+        c128 v = G[i][j];
+        for (int k = 0; k < j; ++k) v = v - G[i][k] * conj(G[j][k]);
+        G[i][j] = (1.0 / ljj) * v;
+      }
+    }
+    for (int k = 0; k < K; ++k) {
+      for (int i = 0; i < nout; ++i) {                // L y = c
+        c128 v = C[i][k];
+        for (int j = 0; j < i; ++j) v = v - G[i][j] * C[j][k];
+        C[i][k] = (1.0 / G[i][i].re) * v;
+      }
+      for (int i = nout - 1; i >= 0; --i) {           // L^dag x = y
+        c128 v = C[i][k];
+        for (int j = i + 1; j < nout; ++j) v = v - cmul_conj(G[j][i], C[j][k]);
+        C[i][k] = (1.0 / G[i][i].re) * v;
+      }
+    }
+  }
+  __syncthreads();
+  double lp = 0;
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+    c128 R[kProjMax];
+    for (int k = 0; k < K; ++k) {
+      c128 v = at(u, k, r);
+      for (int p = 0; p < nout; ++p) v = v - at(X, p, r) * C[p][k];
+      R[k] = v;
+      lp += v.re * v.re + v.im * v.im;
+    }
+    if (gX) {
+      const int comp = 6 * h + r / pg.bvol, site = proj_site(pg.L, pg.agg, blk, r % pg.bvol);
+      for (int p = 0; p < nout; ++p) {
+        c128 gsum = c128{0, 0};
+        for (int k = 0; k < K; ++k) gsum = gsum + R[k] * conj(C[p][k]);
+        gX[((long long)p * 12 + comp) * V + site] = (-2.0 / K) * gsum;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) lp += __shfl_xor(lp, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lp;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    part[blockIdx.x] = t / K;
+    if (bad) atomicOr(status, 1);
+  }
+}
+
 }  // namespace
+
+void launch_proj_loss(const int L[4], const int agg[4], int nout, const c128 *X, int K, const c128 *u, double *part,
+                      double *loss, c128 *gX, int *status, hipStream_t st) {
+  ProjGeom pg;
+  pg.bvol = 1;
+  pg.V = 1;
+  int nblk = 1;
+  for (int m = 0; m < 4; ++m) {
+    pg.L[m] = L[m];
+    pg.agg[m] = agg[m];
+    pg.bvol *= agg[m];
+    pg.V *= L[m];
+    nblk *= L[m] / agg[m];
+  }
+  hipLaunchKernelGGL(k_proj_loss, dim3(2 * nblk), dim3(256), 0, st, pg, nout, X, K, u, part, gX, status);
+  LQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, 2 * nblk, part, loss);
+  LQ_HIP(hipGetLastError());
+}
 
 void launch_mod_relu_backward(int V, int channels, const c128 *phi, const double *b, const c128 *gout, c128 *gphi,
                               double *gb, double *scratch, hipStream_t st) {

@@ -24,7 +24,7 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
-            "lq_mod_relu_backward"]
+            "lq_mod_relu_backward", "lq_proj_loss"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -135,6 +135,7 @@ def load():
         "lq_mod_relu": (i, [vp, i, vp, vp, vp]),
         "lq_ptc_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp]),
         "lq_mod_relu_backward": (i, [vp, i, vp, vp, vp, vp, vp]),
+        "lq_proj_loss": (i, [vp, ip, i, vp, i, vp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -258,6 +259,16 @@ class Context:
                 g, gb[layer] = self.mod_relu_backward(pre[layer], biases[layer], g)
             g, gW[layer] = self.ptc_backward(U, inputs[layer], weights[layer], g)
         return gW, gb
+
+    def proj_loss(self, X: torch.Tensor, u: torch.Tensor, agg, grad: bool = True):
+        """The network's training loss for outputs X [n_out, 12, V] and targets
+        u [K, 12, V] over aggregates agg; returns (loss, dL/dX or None)."""
+        a = (C.c_int * 4)(*agg)
+        loss = C.c_double()
+        g = torch.empty_like(X) if grad else None
+        self._check(self.lib.lq_proj_loss(self.h, a, int(X.shape[0]), _ptr(X.contiguous()), int(u.shape[0]),
+                                          _ptr(u.contiguous()), C.byref(loss), _ptr(g)))
+        return loss.value, g
 
     def lcnn_forward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases):
         """The learned setup's network on the device: the layers and the

@@ -204,6 +204,24 @@ def test_learned_setup_network_gradients_match_oracle_autograd():
         assert np.abs(gb[k].cpu().numpy() - ref).max() < 1e-11 * max(np.abs(ref).max(), 1.0), k
 
 
+def test_learned_setup_loss_and_gradient_match_oracle():
+    # the per-aggregate projection loss and its gradient with respect to the
+    # outputs, against the oracle's loss and autograd
+    from oracle import lcnn
+    dims, agg = (4, 2, 4, 6), (2, 2, 2, 2)
+    lat = Lattice(dims, -1)
+    X = lqsynth.gaussian_spinors(5, dims, 121)
+    u = lqsynth.gaussian_spinors(3, dims, 122)
+    u /= np.linalg.norm(u.reshape(3, -1), axis=1)[:, None, None]
+    Xt = torch.from_numpy(X).requires_grad_(True)
+    L = lcnn.projection_loss(Xt, torch.from_numpy(u), lcnn.block_half_rows(lat, agg))
+    (gX_ref,) = torch.autograd.grad(L, [Xt])
+    c = _ctx(dims, -1)
+    loss, gX = c.proj_loss(dev(X), dev(u), agg)
+    assert abs(loss - L.item()) <= 1e-12 * L.item()
+    assert relmax(host(gX), gX_ref.numpy()) < 1e-10
+
+
 def test_learned_setup_network_forward_matches_oracle():
     # three layers 3 -> 4 -> 4 -> 2 with the nonlinearity between them (biases
     # that cut some sites to zero), device chain against the oracle's forward
