@@ -233,6 +233,16 @@ int lq_mod_relu_backward(lq_ctx *ctx, int channels, const lq_c128 *phi, const do
 int lq_proj_loss(lq_ctx *ctx, const int agg[4], int n_out, const lq_c128 *X, int K, const lq_c128 *u,
                  double *loss, lq_c128 *g_X);
 
+/* One Adam step for the network's training: on n real values (a complex
+ * parameter counts as its real and imaginary parts) with gradient g and
+ * moment estimates m, v (updated in place; zero before the first step),
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr / (1 - b1^t) * m / (sqrt(v / (1 - b2^t)) + eps),
+ * t >= 1 the step number.  All arrays device double.  Asynchronous on the
+ * context's stream.  Errors: LQ_ERR_ARG. */
+int lq_adam_step(lq_ctx *ctx, long long n, double *p, const double *g, double *m, double *v, double lr,
+                 double beta1, double beta2, double eps, int t);
+
 /* ---- dense helper ----------------------------------------------------------- */
 /* Eigen-decomposition of the Hermitian part of the n x n matrix A (host,
  * row-major): w[j] ascending, V (host, row-major) holds the orthonormal

@@ -150,6 +150,9 @@ void launch_ptc_backward(const Geom &g, const c128 *U, int cin, const c128 *phi,
                          const c128 *gout, c128 *gin, c128 *gW, hipStream_t st);
 // out[c] = phi[c] * relu(|phi[c](x)| + b[c]) / |phi[c](x)| (spin-colour norm per site); out may be phi
 void launch_mod_relu(int V, int channels, const c128 *phi, const double *b, c128 *out, hipStream_t st);
+// one Adam step (step number t >= 1) on n real values p with gradient g and moments m, v
+void launch_adam(long long n, double *p, const double *g, double *m, double *v, double lr, double b1, double b2,
+                 double eps, int t, hipStream_t st);
 // training loss of outputs X [nout][12][V] for targets u [K][12][V] over aggregates of extents
 // agg (canonical layout): part [2 * blocks] per-block values, *loss (device) their sum,
 // gX (nullable) the gradient; nout, K <= 32; *status raised if the outputs are dependent

@@ -1611,6 +1611,18 @@ int lq_proj_loss(lq_ctx *c, const int agg[4], int n_out, const lq_c128 *X, int K
   });
 }
 
+int lq_adam_step(lq_ctx *c, long long n, double *p, const double *g, double *m, double *v, double lr, double beta1,
+                 double beta2, double eps, int t) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (n < 0 || (n > 0 && (!p || !g || !m || !v)) || t < 1 || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+      fail(LQ_ERR_ARG, "lq_adam_step: bad arguments");
+    launch_adam(n, p, g, m, v, lr, beta1, beta2, eps, t, c->st);
+    return LQ_OK;
+  });
+}
+
 int lq_coarse_variant(int v) { return coarse_force_variant(v) == 0 ? LQ_OK : LQ_ERR_ARG; }
 
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V) {

@@ -393,7 +393,31 @@ __global__ void __launch_bounds__(256) k_proj_loss(ProjGeom pg, int nout, const 
   }
 }
 
+// One Adam step on n real values (a complex parameter is its real and
+// imaginary parts):  m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+// p -= (lr / bc1) m / (sqrt(v) / sqrt(bc2) + eps),  bc_i = 1 - b_i^t.
+__global__ void k_adam(long long n, double *__restrict__ p, const double *__restrict__ g, double *__restrict__ m,
+                       double *__restrict__ v, double lr, double b1, double b2, double eps, double bc1,
+                       double sbc2) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double gi = g[e];
+  const double mi = b1 * m[e] + (1.0 - b1) * gi;
+  const double vi = b2 * v[e] + (1.0 - b2) * gi * gi;
+  m[e] = mi;
+  v[e] = vi;
+  p[e] -= (lr / bc1) * mi / (sqrt(vi) / sbc2 + eps);
+}
+
 }  // namespace
+
+void launch_adam(long long n, double *p, const double *g, double *m, double *v, double lr, double b1, double b2,
+                 double eps, int t, hipStream_t st) {
+  if (n <= 0) return;
+  const double bc1 = 1.0 - pow(b1, (double)t), sbc2 = sqrt(1.0 - pow(b2, (double)t));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps, bc1, sbc2);
+  LQ_HIP(hipGetLastError());
+}
 
 void launch_proj_loss(const int L[4], const int agg[4], int nout, const c128 *X, int K, const c128 *u, double *part,
                       double *loss, c128 *gX, int *status, hipStream_t st) {

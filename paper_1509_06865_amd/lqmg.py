@@ -24,7 +24,7 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
-            "lq_mod_relu_backward", "lq_proj_loss"]
+            "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -136,6 +136,7 @@ def load():
         "lq_ptc_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp]),
         "lq_mod_relu_backward": (i, [vp, i, vp, vp, vp, vp, vp]),
         "lq_proj_loss": (i, [vp, ip, i, vp, i, vp, dp, vp]),
+        "lq_adam_step": (i, [vp, C.c_longlong, vp, vp, vp, vp, d, d, d, d, i]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -240,10 +241,7 @@ class Context:
                                                   _ptr(g_out.contiguous()), _ptr(g_phi), _ptr(g_b)))
         return g_phi, g_b
 
-    def lcnn_backward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases, g_out: torch.Tensor):
-        """Gradients of a real loss with respect to every weight and bias of the
-        network, given g_out for its output: the forward is rerun to keep each
-        layer's input, then the library's backward calls run in reverse order."""
+    def _forward_keep(self, U, phi0, weights, biases):
         inputs, pre = [], []
         phi = phi0
         for layer, W in enumerate(weights):
@@ -252,6 +250,15 @@ class Context:
             if layer < len(weights) - 1:
                 pre.append(phi)
                 phi = self.mod_relu(phi, biases[layer])
+        return phi, inputs, pre
+
+    def lcnn_backward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases, g_out: torch.Tensor,
+                      kept=None):
+        """Gradients of a real loss with respect to every weight and bias of the
+        network, given g_out for its output: the forward is rerun (or its kept
+        intermediates used) to have each layer's input, then the library's
+        backward calls run in reverse order."""
+        _, inputs, pre = kept if kept is not None else self._forward_keep(U, phi0, weights, biases)
         g = g_out
         gW, gb = [None] * len(weights), [None] * len(biases)
         for layer in range(len(weights) - 1, -1, -1):
@@ -269,6 +276,27 @@ class Context:
         self._check(self.lib.lq_proj_loss(self.h, a, int(X.shape[0]), _ptr(X.contiguous()), int(u.shape[0]),
                                           _ptr(u.contiguous()), C.byref(loss), _ptr(g)))
         return loss.value, g
+
+    def adam_step(self, p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float,
+                  betas=(0.9, 0.999), eps: float = 1e-8, t: int = 1):
+        """One Adam step in place on p (real or complex; complex as real and
+        imaginary parts); m, v are real tensors of p's real view."""
+        pr = torch.view_as_real(p) if p.is_complex() else p
+        gr = torch.view_as_real(g) if g.is_complex() else g
+        self._check(self.lib.lq_adam_step(self.h, pr.numel(), _ptr(pr), _ptr(gr.contiguous()), _ptr(m), _ptr(v),
+                                          float(lr), float(betas[0]), float(betas[1]), float(eps), int(t)))
+
+    def lcnn_train_step(self, U, phi0, weights, biases, u, agg, state, lr, t):
+        """One training step of the network on the device: forward, loss over
+        the aggregates, backward, Adam (step t) on every weight and bias in
+        place.  state: the Adam moments, a list of (m, v) per parameter
+        (weights then biases).  Returns the loss before the update."""
+        out, inputs, pre = self._forward_keep(U, phi0, weights, biases)
+        loss, gX = self.proj_loss(out, u, agg)
+        gW, gb = self.lcnn_backward(U, phi0, weights, biases, gX, kept=(out, inputs, pre))
+        for p, g, (m, v) in zip(list(weights) + list(biases), gW + gb, state):
+            self.adam_step(p, g, m, v, lr, t=t)
+        return loss
 
     def lcnn_forward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases):
         """The learned setup's network on the device: the layers and the

@@ -222,6 +222,49 @@ def test_learned_setup_loss_and_gradient_match_oracle():
     assert relmax(host(gX), gX_ref.numpy()) < 1e-10
 
 
+def test_learned_setup_training_steps_match_oracle():
+    # two training steps on the device (forward, loss, backward, Adam) against
+    # the oracle's network trained by torch's Adam: losses and updated weights
+    from oracle import lcnn
+    dims, agg = (4, 2, 4, 6), (2, 2, 2, 2)
+    lat = Lattice(dims, -1)
+    U = lqsynth.gauge_field(dims, 0.4, 131)
+    phi = lqsynth.gaussian_spinors(3, dims, 132)
+    u = lqsynth.gaussian_spinors(2, dims, 133)
+    u /= np.linalg.norm(u.reshape(2, -1), axis=1)[:, None, None]
+    rng = np.random.default_rng(134)
+    chans = (3, 4, 4)
+    Ws = [(rng.standard_normal((co, ci, 81, 4, 4)) + 1j * rng.standard_normal((co, ci, 81, 4, 4))) / (10 * ci)
+          for ci, co in zip(chans[:-1], chans[1:])]
+    bs = [-0.5 * rng.random(co) for co in chans[1:-1]]
+    params = [torch.from_numpy(w.copy()).requires_grad_(True) for w in Ws] + \
+             [torch.from_numpy(b.copy()).requires_grad_(True) for b in bs]
+    opt = torch.optim.Adam(params, lr=1e-2)
+    trans = lcnn.transports(U, lat)
+    rows = lcnn.block_half_rows(lat, agg)
+    ref_losses = []
+    for _ in range(2):
+        opt.zero_grad()
+        L = lcnn.projection_loss(lcnn.forward(trans, torch.from_numpy(phi), params[:2], params[2:]),
+                                 torch.from_numpy(u), rows)
+        L.backward()
+        opt.step()
+        ref_losses.append(L.item())
+    c = _ctx(dims, -1)
+    dW = [dev(w) for w in Ws]
+    db = [torch.from_numpy(b.copy()).cuda() for b in bs]
+    state = []
+    for p in dW + db:
+        pr = torch.view_as_real(p) if p.is_complex() else p
+        state.append((torch.zeros_like(pr), torch.zeros_like(pr)))
+    losses = [c.lcnn_train_step(dev(U), dev(phi), dW, db, dev(u), agg, state, 1e-2, t) for t in (1, 2)]
+    for a, b in zip(losses, ref_losses):
+        assert abs(a - b) <= 1e-12 * abs(b)
+    for p_dev, p_ref in zip(dW + db, params):
+        ref = p_ref.detach().numpy()
+        assert np.abs(p_dev.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
 def test_learned_setup_network_forward_matches_oracle():
     # three layers 3 -> 4 -> 4 -> 2 with the nonlinearity between them (biases
     # that cut some sites to zero), device chain against the oracle's forward
