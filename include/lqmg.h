@@ -195,7 +195,9 @@ int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c1
  * canonical layout: U [4][9][V] as for q_apply, phi [c_in][12][V],
  * W [c_out][c_in][81][4][4] (spin matrices, row-major), out [c_out][12][V].
  * FP64, asynchronous on the context's stream.  1 <= c_in, c_out <= 64.
- * Errors: LQ_ERR_ARG. */
+ * out must not overlap phi, U or W (every site reads its neighbours' phi).
+ * Sizes cannot be checked here: the caller passes arrays of exactly these
+ * shapes.  Errors: LQ_ERR_ARG. */
 int lq_ptc_forward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
                    const lq_c128 *W, lq_c128 *out);
 /* Gradients through lq_ptc_forward for a real loss L: given g_out =
@@ -203,7 +205,8 @@ int lq_ptc_forward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, 
  * [c_in][12][V]) and g_W (device [c_out][c_in][81][4][4]) of the same form for
  * phi and W; either output may be NULL.  g_in is the adjoint convolution, g_W
  * sums over the sites in a fixed order.  FP64, asynchronous on the context's
- * stream.  Errors: LQ_ERR_ARG. */
+ * stream.  g_in and g_W must not overlap each other or any input.
+ * Errors: LQ_ERR_ARG. */
 int lq_ptc_backward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
                     const lq_c128 *W, const lq_c128 *g_out, lq_c128 *g_in, lq_c128 *g_W);
 /* The network's nonlinearity between layers (gauge invariant): for channel c

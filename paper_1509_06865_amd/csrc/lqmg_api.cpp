@@ -179,6 +179,14 @@ uint64_t key_bits(double d) {
   return u;
 }
 
+// Release every captured graph (after the stream has drained).
+void drop_graphs(lq_ctx *c) {
+  if (c->graphs.empty()) return;
+  sync(c);
+  for (auto &kv : c->graphs) LQ_HIP(hipGraphExecDestroy(kv.second));
+  c->graphs.clear();
+}
+
 // The executable graph of `body` (launches on c->st only, no host waits, no
 // memsets), captured on first use of `key` on a private stream and reused.
 // The cache holds at most 256 graphs; when full it is emptied after the
@@ -186,11 +194,7 @@ uint64_t key_bits(double d) {
 hipGraphExec_t chunk_graph(lq_ctx *c, const std::vector<uint64_t> &key, const std::function<void()> &body) {
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) return it->second;
-  if (c->graphs.size() >= 256) {
-    sync(c);
-    for (auto &kv : c->graphs) LQ_HIP(hipGraphExecDestroy(kv.second));
-    c->graphs.clear();
-  }
+  if (c->graphs.size() >= 256) drop_graphs(c);
   if (!c->cap_st) LQ_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
   const hipStream_t orig = c->st;
   LQ_HIP(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeRelaxed));
@@ -481,8 +485,12 @@ void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, 
     launch_multi_axpy<T>(1, b, 0, n, pp1, r, n, n, nrhs, 1.0, c->st);       // r += b
   };
   int its[kMaxRhs];
+  // every by-value argument of the captured launches belongs to the key: the
+  // coarse lattice extents too (two aggregate shapes with equal nA and n2 must
+  // not share a graph)
   const std::vector<uint64_t> gid = {QcB ? key_bits(QcB) : key_bits(Qc), key_bits(dsig), (uint64_t)c->cg.nA,
-                                     (uint64_t)c->cg.n2,
+                                     (uint64_t)c->cg.n2, (uint64_t)c->cg.nb[0], (uint64_t)c->cg.nb[1],
+                                     (uint64_t)c->cg.nb[2], (uint64_t)c->cg.nb[3],
                                      (uint64_t)variant, key_bits(pm1)};
   gmres_batched<T>(c, kw, n, nrhs, ops, rhs_buf, ec, c->p.coarse_m, c->p.coarse_restarts, c->p.coarse_tol, its,
                    nullptr, 8, graphs ? &gid : nullptr);
@@ -1124,6 +1132,8 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
   return guard(c, [&] {
     check_ctx(c);
     c->have = false;                     // a failed setup leaves no usable hierarchy
+    // graphs captured for the previous hierarchy refer to its buffers and shapes
+    drop_graphs(c);
     if (!U || !agg || !tv0) fail(LQ_ERR_ARG, "mg_setup: NULL pointer");
     int bvol = 1;
     for (int m = 0; m < 4; ++m) {
@@ -1267,7 +1277,8 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     orthonormalise(c, E, nw);
     std::vector<double> lam(nw, 0.0), eps(nw, 1.0);
     c128 *SEL = c->sel.get((size_t)Nv * V12);
-    // P from the current approximations (Alg. 1: "update v_i in P").  With
+    // P from the current approximations (Alg. 1 puts each new iterate into
+    // the interpolation).  With
     // more vectors than Nv it takes the Nv whose lambda lies nearest to one of
     // the shifts about to be solved for (ties: lower index), so that the
     // coarse space holds the near-null vectors of those Q - sigma.

@@ -220,8 +220,10 @@ __global__ void __launch_bounds__(256) k_ptc_grad_weight(Geom g, const c128 *__r
 // phi -> phi * relu(|phi(x)| + b[c]) / |phi(x)| for channel c at site x, with
 // |phi(x)| the norm over the 12 spin-colour components (0 where it vanishes).
 // One thread per (site, channel); out may be phi.
-__global__ void __launch_bounds__(256) k_mod_relu(int V, const c128 *__restrict__ phi, const double *__restrict__ b,
-                                                  c128 *__restrict__ out) {
+// out may be phi (each thread reads its site's 12 components before writing
+// them), so phi and out are not marked restrict
+__global__ void __launch_bounds__(256) k_mod_relu(int V, const c128 *phi, const double *__restrict__ b,
+                                                  c128 *out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= V) return;
   const int ch = blockIdx.y;
@@ -293,8 +295,8 @@ __global__ void __launch_bounds__(256) k_sum_rows(int V, const double *__restric
 //   loss part = sum |R|^2 / K,  gradient rows = -(2/K) R coef^dag
 // (the gradient in the same form as the layer's).  One workgroup per (A, h);
 // G = M^dag M and C = M^dag B accumulate over the rows, thread 0 solves with
-// Cholesky in LDS.  A non-positive pivot (outputs dependent on the block)
-// raises *status.
+// Cholesky in LDS.  A pivot at or below 1e-13 of its diagonal entry (outputs
+// dependent, or nearly so, on the block) raises *status.
 constexpr int kProjMax = 32;
 
 __device__ inline int proj_site(const int L[4], const int agg[4], int blk, int loc) {
@@ -339,9 +341,12 @@ __global__ void __launch_bounds__(256) k_proj_loss(ProjGeom pg, int nout, const 
   if (threadIdx.x == 0) {
     // G = L L^dag in place (lower triangle), then coef = G^-1 C into C
     for (int j = 0; j < nout; ++j) {
-      double dj = G[j][j].re;
+      // the same relative pivot test as the setup's local orthonormalisation:
+      // outputs that are dependent, or nearly so, on the block are rejected
+      const double gjj = G[j][j].re;
+      double dj = gjj;
       for (int k = 0; k < j; ++k) dj -= G[j][k].re * G[j][k].re + G[j][k].im * G[j][k].im;
-      if (!(dj > 0)) { bad = 1; dj = 1.0; }
+      if (!(dj > 1e-13 * gjj) || !(gjj > 0)) { bad = 1; dj = 1.0; }
       const double ljj = sqrt(dj);
       G[j][j] = c128{ljj, 0};
       for (int i = j + 1; i < nout; ++i) {

@@ -154,6 +154,19 @@ def _ptr(t: torch.Tensor | None):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(t: torch.Tensor, name: str, shape, dtype) -> None:
+    """Reject a tensor the library would read out of bounds or misinterpret:
+    the C side cannot check sizes."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
 def _dbl(vals):
     arr = (C.c_double * len(vals))(*[float(v) for v in vals])
     return arr
@@ -208,8 +221,7 @@ class Context:
         """One parallel-transport convolution (complex128): phi [c_in, 12, V],
         W [c_out, c_in, 81, 4, 4] -> [c_out, 12, V]."""
         c_in, c_out = int(phi.shape[0]), int(W.shape[0])
-        if tuple(W.shape) != (c_out, c_in, 81, 4, 4):
-            raise ValueError("W must be [c_out, c_in, 81, 4, 4]")
+        self._net_args(U, phi, W, c_in, c_out)
         out = torch.empty((c_out,) + tuple(phi.shape[1:]), dtype=phi.dtype, device=phi.device)
         self._check(self.lib.lq_ptc_forward(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
                                             _ptr(out)))
@@ -219,22 +231,35 @@ class Context:
         """Gradients (same form as g_out = dL/dRe out + i dL/dIm out) of a real
         loss with respect to phi and W through one layer."""
         c_in, c_out = int(phi.shape[0]), int(W.shape[0])
+        self._net_args(U, phi, W, c_in, c_out)
+        _need(g_out, "g_out", (c_out, 12, self.V), torch.complex128)
         g_in = torch.empty_like(phi)
         g_W = torch.empty_like(W)
         self._check(self.lib.lq_ptc_backward(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
                                              _ptr(g_out.contiguous()), _ptr(g_in), _ptr(g_W)))
         return g_in, g_W
 
+    def _net_args(self, U, phi, W, c_in, c_out):
+        _need(U, "U", (4, 9, self.V), torch.complex128)
+        _need(phi, "phi", (c_in, 12, self.V), torch.complex128)
+        _need(W, "W", (c_out, c_in, 81, 4, 4), torch.complex128)
+
     def mod_relu(self, phi: torch.Tensor, b: torch.Tensor):
         """The network's nonlinearity: phi [C, 12, V] complex128, b [C] float64 (device)."""
+        _need(phi, "phi", (int(phi.shape[0]), 12, self.V), torch.complex128)
         out = torch.empty_like(phi)
         bb = b.to(device=phi.device, dtype=torch.float64).contiguous()
+        _need(bb, "b", (int(phi.shape[0]),), torch.float64)
         self._check(self.lib.lq_mod_relu(self.h, int(phi.shape[0]), _ptr(phi), _ptr(bb), _ptr(out)))
         return out
 
     def mod_relu_backward(self, phi: torch.Tensor, b: torch.Tensor, g_out: torch.Tensor):
         """Gradients through the nonlinearity: (g_phi, g_b)."""
+        C_ = int(phi.shape[0])
+        _need(phi, "phi", (C_, 12, self.V), torch.complex128)
+        _need(g_out, "g_out", (C_, 12, self.V), torch.complex128)
         bb = b.to(device=phi.device, dtype=torch.float64).contiguous()
+        _need(bb, "b", (C_,), torch.float64)
         g_phi = torch.empty_like(phi)
         g_b = torch.empty_like(bb)
         self._check(self.lib.lq_mod_relu_backward(self.h, int(phi.shape[0]), _ptr(phi), _ptr(bb),
@@ -270,6 +295,8 @@ class Context:
     def proj_loss(self, X: torch.Tensor, u: torch.Tensor, agg, grad: bool = True):
         """The network's training loss for outputs X [n_out, 12, V] and targets
         u [K, 12, V] over aggregates agg; returns (loss, dL/dX or None)."""
+        _need(X, "X", (int(X.shape[0]), 12, self.V), torch.complex128)
+        _need(u, "u", (int(u.shape[0]), 12, self.V), torch.complex128)
         a = (C.c_int * 4)(*agg)
         loss = C.c_double()
         g = torch.empty_like(X) if grad else None
@@ -283,6 +310,10 @@ class Context:
         imaginary parts); m, v are real tensors of p's real view."""
         pr = torch.view_as_real(p) if p.is_complex() else p
         gr = torch.view_as_real(g) if g.is_complex() else g
+        for name, t in (("g", gr), ("m", m), ("v", v)):
+            _need(t, name, tuple(pr.shape), torch.float64)
+        if pr.dtype != torch.float64 or pr.device.type != "cuda":
+            raise TypeError("p must be a float64 or complex128 tensor on the HIP device")
         self._check(self.lib.lq_adam_step(self.h, pr.numel(), _ptr(pr), _ptr(gr.contiguous()), _ptr(m), _ptr(v),
                                           float(lr), float(betas[0]), float(betas[1]), float(eps), int(t)))
 

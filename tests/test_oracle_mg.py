@@ -46,6 +46,51 @@ def test_interpolation_orthonormal_and_gamma5_split(setup_small):
         assert set(ag.block[nz]) <= {A}
 
 
+def _local_qr(Wm):
+    """Q factor of the thin QR of Wm with a positive real diagonal of R (unique
+    for full column rank): LAPACK's QR with the phases moved from R to Q."""
+    Qm, Rm = np.linalg.qr(Wm)
+    d = np.diag(Rm)
+    return Qm * (d / np.abs(d))[None, :]
+
+
+def test_interpolation_is_the_local_qr_factor_of_the_test_vectors(setup_small):
+    # sec. 2: P is block diagonal over aggregates and gamma5 halves with
+    # orthonormal columns spanning the test vectors' restrictions; built by
+    # Gram-Schmidt in vector order it is the QR factor of W_{A,h} with a
+    # positive diagonal: span(P_{A,h}[:k]) = span(W_{A,h}[:k]) for every k.
+    s = setup_small
+    ag = s["ag"]
+    Wb, Pb = ag.to_blocks(s["W"]), ag.to_blocks(s["P"])        # [Nv, nA, 2, n]
+    for A in range(ag.nA):
+        for h in range(2):
+            Wm, Pm = Wb[:, A, h, :].T, Pb[:, A, h, :].T
+            assert np.abs(Pm - _local_qr(Wm)).max() < 1e-12
+            C = Pm.conj().T @ Wm                                  # coefficients of W in P
+            assert np.abs(np.tril(C, -1)).max() < 1e-12         # nested spans
+            assert np.all(np.diag(C).real > 0)
+            assert np.abs(Wm - Pm @ C).max() < 1e-12            # W lies in span(P)
+
+
+def test_interpolation_is_invariant_under_global_orthonormalisation(setup_small):
+    # Gram-Schmidt over the whole lattice changes each test vector by earlier
+    # ones with a positive diagonal, an upper-triangular change of basis that
+    # leaves every local QR factor unchanged: P(W) = P(orthonormalise(W)).
+    s = setup_small
+    P2 = M.build_P(M.orthonormalise(s["W"]), s["ag"])
+    assert np.abs(P2 - s["P"]).max() < 1e-12
+
+
+def test_interpolation_rejects_locally_dependent_vectors(setup_small):
+    s = setup_small
+    W = s["W"].copy()
+    # the third vector equals 2x the first on aggregate 0: dependent there only
+    sites = s["ag"].sites[0]
+    W[2][:, sites] = 2.0 * W[0][:, sites]
+    with pytest.raises(np.linalg.LinAlgError):
+        M.build_P(W, s["ag"])
+
+
 def test_restrict_prolong_are_adjoint_dense_products(setup_small):
     s = setup_small
     f = lqsynth.gaussian_spinors(1, DIMS, 8)[0]
