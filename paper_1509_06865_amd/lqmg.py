@@ -310,8 +310,8 @@ class Context:
         imaginary parts); m, v are real tensors of p's real view."""
         pr = torch.view_as_real(p) if p.is_complex() else p
         gr = torch.view_as_real(g) if g.is_complex() else g
-        for name, t in (("g", gr), ("m", m), ("v", v)):
-            _need(t, name, tuple(pr.shape), torch.float64)
+        for name, arr in (("g", gr), ("m", m), ("v", v)):
+            _need(arr, name, tuple(pr.shape), torch.float64)
         if pr.dtype != torch.float64 or pr.device.type != "cuda":
             raise TypeError("p must be a float64 or complex128 tensor on the HIP device")
         self._check(self.lib.lq_adam_step(self.h, pr.numel(), _ptr(pr), _ptr(gr.contiguous()), _ptr(m), _ptr(v),
