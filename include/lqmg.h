@@ -184,6 +184,25 @@ int rqi_lowmodes(lq_ctx *ctx, int n_eig, double tol, double *lambda,
 int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
                       long long n, lq_c128 *out);
 
+/* ---- allocation-free variant ------------------------------------------------ */
+/* Bytes of the fixed device array behind lq_inner_products_noalloc: one copy
+ * per device, held until the process ends. */
+#define LQ_NOALLOC_SCRATCH_BYTES (16 * 1024 * 1024)
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * products as lq_inner_products, with the same arguments, limits and errors,
+ * computed without any device allocation.  Its partial sums and results live
+ * in a fixed device array of LQ_NOALLOC_SCRATCH_BYTES per device; when n is
+ * long the vectors are cut into fewer chunks than lq_inner_products uses
+ * (at most (16 MiB - 64 KiB) / (256 * nb) of them), so the sums may differ by
+ * rounding.  Every call on a device shares that device's array and leaves its
+ * contents behind (no call depends on them): calls that overlap in time on
+ * one device race, so issue them on one stream, one after another.  Returns
+ * after the results are in out (host).  Errors: LQ_ERR_ARG, LQ_ERR_STATE (the
+ * array's address could not be resolved for the device). */
+int lq_inner_products_noalloc(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
+                              long long n, lq_c128 *out);
+
 /* ---- learned setup: network layer (not part of the paper) ------------------- */
 /* One parallel-transport convolution of the network that proposes multigrid
  * test vectors:  out[o](x) = sum_{i < c_in} sum_{d in {-1,0,1}^4}

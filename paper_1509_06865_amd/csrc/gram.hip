@@ -173,14 +173,16 @@ size_t gram_scratch_elems(long long n) {
 }
 
 void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W, long long wstride, long long n,
-                 c128 *out, c128 *scratch, hipStream_t st) {
+                 c128 *out, c128 *scratch, hipStream_t st, long long max_chunks) {
   if (nb <= 0 || nw <= 0) return;
   if (nb > 16 * kGramMaxMT || nw > 16)
     throw HipError(hipErrorInvalidValue, "launch_gram: nb <= 192 and nw <= 16", __FILE__, __LINE__);
+  if (max_chunks < 1) throw HipError(hipErrorInvalidValue, "launch_gram: max_chunks >= 1", __FILE__, __LINE__);
   // chunks of >= 1024 elements, enough of them to give every CU several
   // workgroups (16^4 fields: 768 chunks; 32^3 x 64: the 2048 maximum)
   long long nchunks = (n + 1023) / 1024;
   if (nchunks > kGramMaxChunks) nchunks = kGramMaxChunks;
+  if (nchunks > max_chunks) nchunks = max_chunks;
   if (nchunks < 1) nchunks = 1;
   long long per = (n + nchunks - 1) / nchunks;
   per = ((per + kGramTile - 1) / kGramTile) * kGramTile;

@@ -49,9 +49,13 @@ void launch_arnoldi_solve(int m, int nrhs, const c128 *H, const c128 *g, const i
 // ---- shared-basis products (gram.hip), FP64 -----------------------------------
 // out[i][k] = <E_i, W_k> for i < nb (<= 192), k < nw (<= 16); E_i at E + i*estride,
 // W_k at W + k*wstride, vectors of n complex.  FP64 MFMA, split over n.
+// At most max_chunks element chunks (each leaves nb x 16 complex partial sums
+// in scratch); the scratch must hold min(max_chunks, chunks for n) of them.
 void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W, long long wstride, long long n,
-                 c128 *out /*device [nb][nw]*/, c128 *scratch, hipStream_t st);
+                 c128 *out /*device [nb][nw]*/, c128 *scratch, hipStream_t st, long long max_chunks = 2048);
 size_t gram_scratch_elems(long long n);
+// complex partial sums one element chunk of the Gram kernel leaves for nb basis vectors
+inline size_t gram_chunk_elems(int nb) { return (size_t)nb * 16; }
 // U_k (+)= sum_i Y[i][k] E_i for k < nw; Y device [nb][nw].
 void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128 *Y, c128 *U, long long ustride,
                     long long n, bool accumulate, hipStream_t st);

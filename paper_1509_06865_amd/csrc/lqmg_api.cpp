@@ -16,6 +16,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -169,6 +170,42 @@ struct lq_ctx {
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free entry point (lq_inner_products_noalloc):
+// a fixed array in the library's code object, one copy per device, held until
+// the process ends.  Host code never uses its name as an address: each
+// device's address is resolved once, with that device current, and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)LQ_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kNoAllocOutBytes = 64 * 1024;          // [nb][nw] results, nb <= 192, nw <= 16
+static_assert(192 * 16 * sizeof(c128) <= kNoAllocOutBytes, "result area too small");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve the scratch array's address on device dev (current).  Returns false
+// if the runtime cannot give it.
+bool resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return true;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return false;
+  }
+  g_scratch_ptr[dev] = p;
+  return true;
+}
+
+void *scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 void sync(lq_ctx *c) { LQ_HIP(hipStreamSynchronize(c->st)); }
 
@@ -1075,6 +1112,9 @@ int lq_create(lq_ctx **out, const int dims[4], int t_bc, void *stream) {
   c->st = (hipStream_t)stream;
   c->gcan = make_geom(dims, dims, t_bc);
   if (hipGetDevice(&c->dev) != hipSuccess) { delete c; return LQ_ERR_HIP; }
+  // the allocation-free entry point's scratch, once per device (set-up time);
+  // a failure only disables that entry point (it then returns LQ_ERR_STATE)
+  (void)resolve_scratch(c->dev);
   lq_params_default(&c->p);
   int rc = guard(c, [&] {
     std::vector<c128> m1(kMaxRhs, c128{-1.0, 0.0}), p1(kMaxRhs, c128{1.0, 0.0});
@@ -1672,6 +1712,26 @@ int lq_inner_products(lq_ctx *c, int nb, const lq_c128 *E, int nw, const lq_c128
       fail(LQ_ERR_ARG, "lq_inner_products: bad arguments");
     auto g = gram(c, nb, (const c128 *)E, n, nw, (const c128 *)W, n, n);
     std::memcpy(out, g.data(), g.size() * sizeof(cd));
+    return LQ_OK;
+  });
+}
+
+int lq_inner_products_noalloc(lq_ctx *c, int nb, const lq_c128 *E, int nw, const lq_c128 *W, long long n,
+                              lq_c128 *out) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (nb < 1 || nb > 192 || nw < 1 || nw > 16 || n < 1 || !E || !W || !out)
+      fail(LQ_ERR_ARG, "lq_inner_products_noalloc: need 1 <= nb <= 192, 1 <= nw <= 16, n >= 1, non-NULL pointers");
+    unsigned char *base = static_cast<unsigned char *>(scratch_on(c->dev));
+    if (!base) fail(LQ_ERR_STATE, "lq_inner_products_noalloc: no scratch address for this device");
+    // results first, then as many element chunks of partial sums as fit
+    c128 *dout = reinterpret_cast<c128 *>(base);
+    c128 *part = reinterpret_cast<c128 *>(base + kNoAllocOutBytes);
+    const long long max_chunks =
+        (long long)((kNoAllocBytes - kNoAllocOutBytes) / (gram_chunk_elems(nb) * sizeof(c128)));
+    launch_gram(nb, (const c128 *)E, n, nw, (const c128 *)W, n, n, dout, part, c->st, max_chunks);
+    LQ_HIP(hipMemcpyAsync(out, dout, (size_t)nb * nw * sizeof(c128), hipMemcpyDeviceToHost, c->st));
+    sync(c);
     return LQ_OK;
   });
 }

@@ -24,7 +24,7 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
-            "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step"]
+            "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -127,6 +127,7 @@ def load():
         "mg_smooth": (i, [vp, i, dp, vp, vp, i]),
         "mg_cycle": (i, [vp, i, dp, vp, vp]),
         "lq_inner_products": (i, [vp, i, vp, i, vp, C.c_longlong, vp]),
+        "lq_inner_products_noalloc": (i, [vp, i, vp, i, vp, C.c_longlong, vp]),
         "lq_kernel_timer_start": (i, [i]),
         "lq_kernel_timer_read": (i, [C.POINTER(C.c_longlong), dp, dp]),
         "lq_herm_eigh": (i, [i, vp, vp, vp]),
@@ -411,6 +412,17 @@ class Context:
         out = np.empty((nb, nw), dtype=np.complex128)
         self._check(self.lib.lq_inner_products(self.h, nb, _ptr(E), nw, _ptr(W), n,
                                                C.c_void_p(out.ctypes.data)))
+        return out
+
+    def inner_products_noalloc(self, E, W):
+        """As inner_products, through the entry point that allocates no device
+        memory (its partial sums live in the library's fixed scratch array)."""
+        import numpy as np
+        nb, nw = E.shape[0], W.shape[0]
+        n = E[0].numel()
+        out = np.empty((nb, nw), dtype=np.complex128)
+        self._check(self.lib.lq_inner_products_noalloc(self.h, nb, _ptr(E), nw, _ptr(W), n,
+                                                       C.c_void_p(out.ctypes.data)))
         return out
 
     def cycle(self, sigma, r):
