@@ -111,26 +111,118 @@ def time_q_apply(ctx, U, m0, x, reps, torch):
     return start.elapsed_time(stop) / reps / 1e3
 
 
-def cpu_baseline(U_host, m0, dims, t_bc, x_host, n_outer):
-    """The oracle's FP64 Q apply (definition route) timed on the host on the
-    full lattice, scaled by the step's outer FGMRES iterations (each applies Q
-    once): a lower bound on the oracle's time for the same eigensolve, which
-    also needs the smoother, the coarse solves and the orthogonalisation."""
-    from oracle.dirac import Lattice, apply_Q
+def host_cpu_info():
+    """(logical CPUs, CPU model) of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+_ORACLE = {}
+
+
+def _oracle_init(dims, t_bc, eps, seed, m0, agg, sweeps, n_mr, barrier):
+    """Worker set-up: the oracle's operator on the benchmark field (generated
+    again from its seed) and four seeded vectors."""
+    import lqsynth
+    from oracle import mg as M
+    from oracle.dirac import Lattice, WilsonOp
     lat = Lattice(dims, t_bc)
-    lat.tables()                                   # neighbour tables built outside the timing
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        apply_Q(U_host, m0, x_host, lat)
-        reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 3:
-            break
-    t = (time.perf_counter() - t0) / reps
-    return {"value": round(t * n_outer, 1), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} FP64 Q applies of the oracle's numpy definition on the full {dims} lattice, "
-                      f"{t:.2f} s each, times the {n_outer} outer FGMRES iterations of the GPU step (one Q "
-                      f"apply each): a lower bound for the oracle's eigensolve, whose smoother, coarse solves "
-                      f"and orthogonalisation are not counted"}
+    op = WilsonOp(lqsynth.gauge_field(dims, eps, seed), m0, lat)
+    _ORACLE.update(op=op, ag=M.Aggregation(lat, agg), x=lqsynth.gaussian_spinors(4, dims, 11), sweeps=sweeps,
+                   n_mr=n_mr, barrier=barrier)
+
+
+def _oracle_iteration(k):
+    """One worker's share of the sample: the fine-level work of one outer
+    FGMRES iteration of the oracle's solver on its own right-hand side (the
+    FP64 Q apply and the smoother's sweeps), timed in the worker."""
+    from oracle import mg as M
+    o = _ORACLE
+    x = o["x"][k % len(o["x"])]
+    o["barrier"].wait(timeout=900)        # every worker starts at once: all cores busy
+    t0 = time.perf_counter()
+    o["op"].Q(x)
+    M.sap(o["op"], o["ag"], 0.01 * k, x, o["sweeps"], o["n_mr"])
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(dims, t_bc, eps, seed, m0, agg, nv, prm, n_outer, n_rebuild, cores):
+    """The oracle (numpy, FP64) timed on this host on a bounded sample of the
+    benchmark step, scaled by the step's own counts:
+      * `cores` worker processes run at once, each the fine-level work of one
+        outer FGMRES iteration (a Q apply and the smoother's SAP sweeps) on its
+        own vector: the wall time over `cores` is the cost per iteration with
+        every core busy (the iterations of a block of shifted solves are
+        independent);
+      * the coarse operator of a 2-column interpolation (a tenth of one
+        rebuild's columns at Nv = 20) times Nv, per rebuild.
+    The coarse solves, the Gram-Schmidt and Rayleigh-Ritz products are not
+    counted, so the figure is a lower bound of the oracle's time."""
+    import multiprocessing as mp
+
+    import lqsynth
+    from oracle import mg as M
+    from oracle.dirac import Lattice, WilsonOp
+    # fresh interpreters (no state of this process, which holds the GPU)
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(cores)
+    with ctx.Pool(cores, initializer=_oracle_init,
+                  initargs=(dims, t_bc, eps, seed, m0, agg, prm["post"], prm["sap_mr"], barrier)) as pool:
+        # one task per worker: each waits at the barrier until all have started
+        per_worker = pool.map(_oracle_iteration, range(cores), chunksize=1)
+    wall = max(per_worker)
+    t_iter = wall / cores
+    lat = Lattice(dims, t_bc)
+    op = WilsonOp(lqsynth.gauge_field(dims, eps, seed), m0, lat)
+    ag = M.Aggregation(lat, agg)
+    t0 = time.perf_counter()
+    M.coarse_operator(op, ag, M.build_P(lqsynth.gaussian_spinors(1, dims, 12), ag))
+    t_cols = time.perf_counter() - t0           # 2 of the 2 Nv columns
+    t_rebuild = t_cols * nv
+    value = n_outer * t_iter + n_rebuild * t_rebuild
+    return {"value": round(value, 1), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle on this host ({host_cpu_info()[1]}, {host_cpu_info()[0]} logical CPUs): "
+                      f"{cores} processes at once, each one outer FGMRES iteration's fine-level work (FP64 Q apply + "
+                      f"{prm['post']} SAP sweeps of {prm['sap_mr']} MR steps on {agg} blocks) on the {dims} lattice: "
+                      f"{min(per_worker):.1f}-{wall:.1f} s per process, {wall:.1f} s for all = "
+                      f"{t_iter:.3f} s per iteration x {n_outer} outer iterations of the GPU step; plus the coarse "
+                      f"operator of 2 interpolation columns ({t_cols:.1f} s, one core) x Nv = {nv} per rebuild x "
+                      f"{n_rebuild} rebuilds.  Coarse solves, Gram-Schmidt and Rayleigh-Ritz are not counted: a lower "
+                      f"bound",
+            "per_iteration_s": round(t_iter, 4), "rebuild_s": round(t_rebuild, 1)}
+
+
+def _tiny_oracle_solve(q):
+    """The oracle's complete eigensolve on the tiny periodic lattice (4^4):
+    adaptive setup and Alg. 1 with a Rayleigh-Ritz step per pass, the 8
+    lowest pairs at 1e-10, one core.  Runs in a child process."""
+    try:
+        import lqsynth
+        from oracle import mg as M
+        from oracle import rqi as R
+        from oracle.dirac import Lattice, WilsonOp
+        g = load_golden("tiny_periodic")
+        dims = tuple(g["dims"])
+        U = lqsynth.gauge_field(dims, g["eps"], g["field_seed"])
+        op = WilsonOp(U, g["m0"], Lattice(dims, g["t_bc"]))
+        t0 = time.perf_counter()
+        mg, W = M.setup(op, (2, 2, 2, 2), lqsynth.gaussian_spinors(8, dims, 102),
+                        M.MGParams(coarse_m=128, coarse_tol=1e-8, coarse_restarts=2, n_setup=4))
+        V0 = np.concatenate([W, lqsynth.gaussian_spinors(2, dims, 103)])
+        lam, v, eps, info = R.rqi(mg, V0, 1e-10, W_pad=W, solve_tol=1e-6, max_sweeps=10, rayleigh_ritz=True,
+                                  n_want=8)
+        q.put({"s": round(time.perf_counter() - t0, 2), "converged": info["converged"], "sweeps": info["sweeps"],
+               "lambda": [float(x) for x in lam[:8]]})
+    except Exception as e:                      # reported, never fatal to the benchmark
+        q.put({"error": repr(e)})
 
 
 # kernel classes of the library's timer (paper_1509_06865_amd.KT_*) and how
@@ -278,9 +370,19 @@ def main():
     if args.roofline_class == "all":
         ap.error("--roofline-class all is for --kernel-only runs")
 
+    # the oracle's complete tiny solve runs on one host core beside the GPU work
+    tiny_proc = tiny_q = None
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        sctx = mp.get_context("spawn")
+        tiny_q = sctx.Queue()
+        tiny_proc = sctx.Process(target=_tiny_oracle_solve, args=(tiny_q,), daemon=True)
+        tiny_proc.start()
+
     import torch
     import lqsynth
     from paper_1509_06865_amd import Context, MGParams
+    from paper_1509_06865_amd import load as load_lib
 
     wl = dict(WORKLOADS[args.workload])
     wl["params"] = dict(wl["params"])
@@ -404,10 +506,45 @@ def main():
         del bU, bx, bctx
     else:
         out["config"]["dirac_apply_gbs_32x32x32x64"] = out["config"]["dirac_apply_gbs"]
+    gpu_tiny = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle Q apply on the host)")
-        x_host = x[0].cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(U_host, m0, dims, t_bc, x_host, info["fgmres_iters"])
+        # the GPU's time for the oracle's tiny solve (same lattice, field, start vectors, 8 lowest pairs)
+        tw = WORKLOADS["small"]
+        tg = load_golden(tw["golden"])
+        tdims = tuple(tg["dims"])
+        tU = torch.from_numpy(lqsynth.gauge_field(tdims, tg["eps"], tg["field_seed"])).cuda()
+        ttv = torch.from_numpy(lqsynth.gaussian_spinors(tw["nv"], tdims, 102)).cuda()
+        tV0 = torch.from_numpy(lqsynth.gaussian_spinors(tw["guard"], tdims, 103)).cuda()
+        tctx = Context(tdims, tg["t_bc"])
+        tprm = MGParams(precision=1, rqi_guard=tw["guard"], rayleigh_ritz=1, **tw["params"])
+        torch.cuda.synchronize()
+        a = time.time()
+        tctx.mg_setup(tU, tg["m0"], tw["agg"], ttv, tprm)
+        _, _, _, tinfo = tctx.rqi_lowmodes(tw["n_eig"], tw["tol"], V0=tV0)
+        torch.cuda.synchronize()
+        gpu_tiny = round(time.time() - a, 3)
+        log(f"tiny workload on the GPU: {gpu_tiny} s, converged {tinfo['converged']}")
+        del tctx
+    if not args.no_cpu_baseline:
+        cores = min(16, host_cpu_info()[0])
+        log(f"cpu baseline: the oracle on {cores} host processes")
+        eff = prm.to_c(load_lib())
+        out["cpu_baseline"] = cpu_baseline(dims, t_bc, eps, seed, m0, wl["agg"], wl["nv"],
+                                           {"post": eff.post, "sap_mr": eff.sap_mr}, info["fgmres_iters"],
+                                           info["p_rebuilds"], cores)
+        if tiny_proc is not None:
+            import queue
+            try:
+                tiny = tiny_q.get(timeout=600)
+            except queue.Empty:
+                tiny = {"error": "no result within 600 s"}
+            tiny_proc.join(timeout=30)
+            out["cpu_baseline"]["tiny_full_solve"] = dict(
+                tiny, what="the oracle's complete setup + Alg. 1 (Rayleigh-Ritz per pass, 8 lowest pairs at 1e-10, "
+                           "4^4 periodic) on one core, run beside the GPU steps")
+            if gpu_tiny is not None:
+                out["cpu_baseline"]["tiny_full_solve"]["gpu_s"] = gpu_tiny
+        log(f"cpu baseline: {out['cpu_baseline']['value']} s (lower bound for the step)")
     print(json.dumps(out), flush=True)
 
 
