@@ -403,3 +403,202 @@ def setup(op: WilsonOp, agg, W0, params: MGParams | None = None):
         W = orthonormalise(W)
         mg.set_vectors(W)
     return mg, W
+
+
+# ---------------------------------------------------------------------------
+# a third level: aggregation of the coarse lattice (the paper's hierarchy is
+# two-level; the 32^3 x 64 workload adds one level below it)
+# ---------------------------------------------------------------------------
+#
+# Level-1 vectors are [..., nA1, 2 Nv1] (sites of the coarse lattice, index
+# h*Nv1 + k inside a site, h the gamma5^c half).  The level-1 sites are cut
+# into blocks of extent agg2 of the coarse lattice; P2 holds Nv2 level-1
+# vectors whose restriction to (level-2 aggregate A2, half h) are orthonormal
+# columns, so gamma5^c P2 = P2 gamma5^c2 and P2^dag P2 = 1 as on the first
+# level; Q_c2 = P2^dag Q_c P2 is again a nine-point stencil of dense blocks.
+
+def coarse_lattice(ag: Aggregation) -> Lattice:
+    """The lattice of aggregates (coarse sites; boundary signs live in Q_c)."""
+    return Lattice(ag.nb, 1)
+
+
+def coarse_to_blocks(ag2: Aggregation, v, Nv1: int):
+    """[..., nA1, 2 Nv1] -> [..., nA2, 2, bvol2 * Nv1] (level-2 aggregate, half, local)."""
+    lead = v.shape[:-2]
+    g = v.reshape(lead + (v.shape[-2], 2, Nv1))[..., ag2.sites, :, :]      # [..., nA2, bvol2, 2, Nv1]
+    g = np.moveaxis(g, -2, -3)                                              # [..., nA2, 2, bvol2, Nv1]
+    return g.reshape(lead + (ag2.nA, 2, ag2.bvol * Nv1))
+
+
+def coarse_from_blocks(ag2: Aggregation, g, Nv1: int):
+    lead = g.shape[:-3]
+    g = g.reshape(lead + (ag2.nA, 2, ag2.bvol, Nv1))
+    g = np.moveaxis(g, -3, -2)                                              # [..., nA2, bvol2, 2, Nv1]
+    v = np.empty(lead + (ag2.lat.V, 2, Nv1), dtype=g.dtype)
+    v[..., ag2.sites, :, :] = g
+    return v.reshape(lead + (ag2.lat.V, 2 * Nv1))
+
+
+def local_gram_schmidt(Wb):
+    """Per block and half, Gram-Schmidt (twice) in vector order and
+    normalisation of Wb [Nv, ..., n] over its last axis."""
+    Nv = Wb.shape[0]
+    Pb = np.empty_like(Wb)
+    for k in range(Nv):
+        w = Wb[k].copy()
+        for _ in range(2):
+            for j in range(k):
+                w = w - np.sum(np.conj(Pb[j]) * w, axis=-1)[..., None] * Pb[j]
+        nrm = np.sqrt(np.sum(np.abs(w) ** 2, axis=-1))
+        if np.any(nrm < 1e-12):
+            raise np.linalg.LinAlgError("test vectors are locally rank deficient")
+        Pb[k] = w / nrm[..., None]
+    return Pb
+
+
+def build_P2(W1, ag2: Aggregation, Nv1: int):
+    """Level-2 interpolation from level-1 test vectors W1 [Nv2, nA1, 2 Nv1]."""
+    Wb = coarse_to_blocks(ag2, np.asarray(W1, dtype=np.complex128), Nv1)
+    return coarse_from_blocks(ag2, local_gram_schmidt(Wb), Nv1)
+
+
+def restrict2(P2, ag2: Aggregation, v, Nv1: int):
+    """P2^dag v: [..., nA1, 2 Nv1] -> [..., nA2, 2 Nv2]."""
+    Pb = coarse_to_blocks(ag2, P2, Nv1)                 # [Nv2, nA2, 2, n]
+    vb = coarse_to_blocks(ag2, v, Nv1)                  # [..., nA2, 2, n]
+    c = np.einsum("kahn,...ahn->...ahk", np.conj(Pb), vb)
+    return c.reshape(c.shape[:-2] + (2 * P2.shape[0],))
+
+
+def prolong2(P2, ag2: Aggregation, c, Nv1: int):
+    """P2 c: [..., nA2, 2 Nv2] -> [..., nA1, 2 Nv1]."""
+    Nv2 = P2.shape[0]
+    Pb = coarse_to_blocks(ag2, P2, Nv1)                 # [Nv2, nA2, 2, n]
+    cb = c.reshape(c.shape[:-1] + (2, Nv2))             # [..., nA2, 2, Nv2]
+    return coarse_from_blocks(ag2, np.einsum("kahn,...ahk->...ahn", Pb, cb), Nv1)
+
+
+def coarse_half_columns(P2, Nv1: int):
+    """The 2 Nv2 columns of P2 as level-1 vectors: column h*Nv2 + l is P2_l with
+    the other gamma5^c half set to zero."""
+    Nv2 = P2.shape[0]
+    v = P2.reshape(Nv2, P2.shape[1], 2, Nv1)
+    cols = np.zeros((2 * Nv2,) + v.shape[1:], dtype=np.complex128)
+    cols[:Nv2, :, 0] = v[:, :, 0]
+    cols[Nv2:, :, 1] = v[:, :, 1]
+    return cols.reshape(2 * Nv2, P2.shape[1], 2 * Nv1)
+
+
+def coarse_operator2(Qc, ag1: Aggregation, ag2: Aggregation, P2):
+    """Q_c2 = P2^dag Q_c P2 as [nA2, 9, 2 Nv2, 2 Nv2]: each coupling term d of
+    Q_c (source nb(A1, d), target A1) is assigned to the self block when both
+    sites lie in one level-2 aggregate, else to the level-2 direction d."""
+    Nv1 = Qc.shape[-1] // 2
+    Nv2 = P2.shape[0]
+    n = 2 * Nv2
+    internal = [np.ones(ag1.nA, dtype=bool)]
+    internal += [ag2.int_fwd[m] for m in range(4)] + [ag2.int_bwd[m] for m in range(4)]
+    Qc2 = np.zeros((ag2.nA, 9, n, n), dtype=np.complex128)
+    for j, x in enumerate(coarse_half_columns(P2, Nv1)):
+        parts = np.zeros((9,) + x.shape, dtype=np.complex128)
+        for d in range(9):
+            term = np.einsum("aij,aj->ai", Qc[:, d], x[ag1.cnbr[:, d]])
+            parts[0] += term * internal[d][:, None]
+            if d > 0:
+                parts[d] += term * (~internal[d])[:, None]
+        Qc2[:, :, :, j] = np.moveaxis(restrict2(P2, ag2, parts, Nv1), 0, 1)
+    return Qc2
+
+
+@dataclass
+class Level2Params:
+    post: int = 2                # level-1 post-smoothing steps
+    m_smooth: int = 4            # GMRES steps per level-1 smoothing step (on gamma5^c (Q_c - sigma))
+    coarse_m: int = 40           # level-2 GMRES restart length
+    coarse_tol: float = 0.05     # level-2 GMRES relative residual target
+    coarse_restarts: int = 4
+    coarse_direct: bool = False  # exact dense level-2 solve
+
+
+class ThreeLevel(TwoLevel):
+    """Three levels: the level-1 system (Q_c - sigma) e = c of the two-grid
+    cycle is solved by FGMRES (restart coarse_m, relative coarse_tol) right-
+    preconditioned by a level-1 two-grid cycle: the level-2 correction
+    P2 (Q_c2 - sigma)^{-1} P2^dag r, then `post` smoothing steps of GMRES on
+    the gamma5^c form of Q_c - sigma."""
+
+    def __init__(self, op: WilsonOp, agg, agg2, params: MGParams | None = None,
+                 params2: Level2Params | None = None):
+        super().__init__(op, agg, params)
+        self.agg2 = tuple(int(a) for a in agg2)
+        self.ag2 = Aggregation(coarse_lattice(self.ag), self.agg2)
+        self.params2 = params2 or Level2Params()
+        self.P2 = None
+        self.Qc2 = None
+        self._Qc2_dense = None
+
+    def set_vectors(self, W, W2=None):
+        """P, Q_c from the fine test vectors W; P2, Q_c2 from the level-1 test
+        vectors W2 [Nv2, nA1, 2 Nv1] (default: the restrictions P^dag W)."""
+        super().set_vectors(W)
+        if W2 is None:
+            W2 = restrict(self.P, self.ag, np.asarray(W, dtype=np.complex128))
+        self.set_level2(W2)
+
+    def set_level2(self, W2):
+        Nv1 = self.P.shape[0]
+        self.P2 = build_P2(W2, self.ag2, Nv1)
+        self.Qc2 = coarse_operator2(self.Qc, self.ag, self.ag2, self.P2)
+        self._Qc2_dense = None
+
+    def A1(self, sigma, v):
+        return coarse_apply(self.Qc, self.ag, v, sigma)
+
+    def solve2(self, sigma, c2):
+        """(Q_c2 - sigma) e = c2: GMRES on the gamma5^c2 form, or exact."""
+        p = self.params2
+        if p.coarse_direct:
+            if self._Qc2_dense is None:
+                self._Qc2_dense = dense_coarse(self.Qc2, self.ag2)
+            M = self._Qc2_dense - sigma * np.eye(self._Qc2_dense.shape[0])
+            return np.linalg.solve(M, c2.reshape(-1)).reshape(c2.shape)
+        g5 = coarse_gamma5(self.P2.shape[0])
+
+        def op(v):
+            return g5 * coarse_apply(self.Qc2, self.ag2, v, sigma)
+
+        rhs = g5 * c2
+        e = np.zeros_like(c2)
+        target = p.coarse_tol * norm(c2)
+        for _ in range(p.coarse_restarts + 1):
+            res = rhs - op(e)
+            if norm(res) <= target:
+                break
+            e = e + gmres(op, res, p.coarse_m, target / max(norm(res), 1e-300))[0]
+        return e
+
+    def smooth1(self, sigma, r, steps):
+        """Level-1 smoother: each step m_smooth GMRES steps on
+        gamma5^c (Q_c - sigma) for the current residual."""
+        g5 = coarse_gamma5(self.P.shape[0])
+        z = np.zeros_like(r)
+        for _ in range(steps):
+            res = g5 * (r - self.A1(sigma, z))
+            z = z + gmres(lambda v: g5 * self.A1(sigma, v), res, self.params2.m_smooth, 0.0)[0]
+        return z
+
+    def cycle1(self, sigma, r):
+        """Level-1 two-grid cycle B1 ~ (Q_c - sigma)^{-1}."""
+        Nv1 = self.P.shape[0]
+        z = prolong2(self.P2, self.ag2, self.solve2(sigma, restrict2(self.P2, self.ag2, r, Nv1)), Nv1)
+        if self.params2.post > 0:
+            z = z + self.smooth1(sigma, r - self.A1(sigma, z), self.params2.post)
+        return z
+
+    def coarse_solve(self, sigma, c):
+        p = self.params
+        if p.coarse_direct:
+            return super().coarse_solve(sigma, c)
+        x, _ = fgmres(lambda v: self.A1(sigma, v), lambda v: self.cycle1(sigma, v), c, p.coarse_m,
+                      p.coarse_tol, p.coarse_restarts)
+        return x
