@@ -241,7 +241,7 @@ KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
 def coarse_variants(args):
     """Time each coarse-apply kernel (0: one wave per (site, field); 1-3: LDS-staged
     blocks for 4, 8, 16 fields per pass; 4, 5: as 1, 2 per (site, chunk of
-    fields)) with the FP32 coarse operator and with its bfloat16 copy, on the
+    fields); 6: matrix cores) with the FP32 coarse operator and with its bfloat16 copy, on the
     coarse grid of a 16^3 x 32 lattice with 2^4 aggregates and Nv = 24 (8192
     coarse sites, 48 x 48 blocks), 16 fields, through the library's kernel timer.
     Prints one JSON line per (storage, kernel)."""
@@ -262,7 +262,7 @@ def coarse_variants(args):
     for bf16 in (0, 1):
         ctx = Context(dims, 1)
         ctx.mg_setup(U, -0.15, agg, tv0, MGParams(precision=1, n_setup=0, n_init=1, coarse_bf16=bf16))
-        for v in range(6):
+        for v in range(7):
             coarse_variant(v)
             ctx.coarse_apply(sig, x)
             torch.cuda.synchronize()

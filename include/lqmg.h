@@ -275,16 +275,19 @@ int lq_adam_step(lq_ctx *ctx, long long n, double *p, const double *g, double *m
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V);
 
 /* ---- coarse-apply kernel choice --------------------------------------------- */
-/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has six
+/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has seven
  * kernels: 0 one wavefront per (coarse site, rhs); 1, 2, 3 one workgroup per
  * coarse site with each 2Nv x 2Nv block staged in LDS and applied to 4, 8 or
  * 16 right-hand sides per pass; 4, 5 as 1, 2 with one workgroup per (coarse
- * site, chunk of 4 or 8 right-hand sides).  By default each coarse solve
- * times the six on its first call for a shape (precision, coarse sites, 2Nv,
- * rhs count, device) and keeps the fastest for the process.
- * lq_coarse_variant(v) with v in 0..5 forces kernel v for every shape (tests
+ * site, chunk of 4 or 8 right-hand sides); 6 the matrix-core kernel (FP32
+ * arithmetic on FP32 or bfloat16 storage, one workgroup per (coarse site,
+ * 16 right-hand sides), 2Nv a multiple of 8 up to 64; where it does not apply
+ * kernel 2 runs instead).  By default each coarse solve times the applicable
+ * kernels on its first call for a shape (precision, coarse sites, 2Nv, rhs
+ * count, device) and keeps the fastest for the process.
+ * lq_coarse_variant(v) with v in 0..6 forces kernel v for every shape (tests
  * compare them); v = -1 returns to the tuned choice.  Process-wide, not
- * thread-safe.  Errors: LQ_ERR_ARG for v outside -1..5. */
+ * thread-safe.  Errors: LQ_ERR_ARG for v outside -1..6. */
 int lq_coarse_variant(int v);
 
 /* ---- kernel timing (measurement of the hot kernels against the roofline) -- */

@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "lq_kernels.h"
 
@@ -165,6 +166,100 @@ __global__ void __launch_bounds__(256) k_coarse_apply_multi(CoarseGeom cg, const
   }
 }
 
+// Matrix-core form (FP32 arithmetic; blocks stored in FP32 or bfloat16).  One
+// workgroup per (coarse site, chunk of 16 right-hand sides) and one wave per
+// 8 complex rows of the site's output, n2 / 8 waves.  For each of the nine
+// couplings the 2Nv x 2Nv block and the neighbour's 16 vectors are staged in
+// LDS (the next block is prefetched into registers meanwhile), and the complex
+// product runs as real 16x16x4 MFMAs on an interleaved embedding: real row
+// 2i + ri is (Re, Im) of complex row i, real k index 2j + kj is (Re, Im) of
+// complex column j, so that
+//   A[2i+ri][2j+kj] = Re M_ij (ri == kj), -Im M_ij (ri = 0, kj = 1), Im M_ij (ri = 1, kj = 0)
+// for a stored block and the same with conj(M_ji) for a backward (conjugate
+// transposed) one, and B[2j+kj][k] = (Re, Im) of x_k[j].  One MFMA consumes two
+// complex columns; every multiply it does is a term of the complex product.
+// Layouts of v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register r of lane l is D[4 (l / 16) + r][l % 16].
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kMfmaRhs = 16;
+constexpr int kMfmaMaxN2 = 64;
+constexpr int kMfmaPre = kMfmaMaxN2 / 8;     // block elements per thread: n2^2 / (8 n2)
+
+template <typename QT>
+__global__ void __launch_bounds__(512) k_coarse_apply_mfma(CoarseGeom cg, const QT *__restrict__ Qc,
+                                                           const c64 *__restrict__ xin, c64 *__restrict__ yout,
+                                                           Shifts sig, const double *__restrict__ dsig, bool g5form,
+                                                           int nrhs) {
+  __shared__ c64 blk[kMfmaMaxN2 * (kMfmaMaxN2 + 1)];
+  __shared__ c64 xs[kMfmaMaxN2 * (kMfmaRhs + 1)];
+  const int A = blockIdx.x, k0 = blockIdx.y * kMfmaRhs;
+  const int n2 = cg.n2, ld = n2 + 1, ldx = kMfmaRhs + 1;
+  const int kc = (nrhs - k0 < kMfmaRhs) ? nrhs - k0 : kMfmaRhs;
+  const int t = threadIdx.x, nthr = blockDim.x;
+  const int lane = t & 63, w = t >> 6;
+  int nb[9];
+  nb[0] = A;
+  for (int mu = 0; mu < 4; ++mu) { nb[1 + mu] = cnbr(cg, A, mu, 1); nb[5 + mu] = cnbr(cg, A, mu, -1); }
+  const long long bs = (long long)n2 * n2;
+  auto block_ptr = [&](int d) -> const QT * {
+    return (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
+  };
+  // this lane's operand coordinates
+  const int ci = 8 * w + ((lane & 15) >> 1), ri = lane & 1;     // A row: complex row, Re/Im
+  const int kq = lane >> 4, kj = kq & 1;                      // k index in the step
+  const int col = lane & 15;                                  // B / D column: right-hand side
+  c64 pre[kMfmaPre];
+#pragma unroll
+  for (int q = 0; q < kMfmaPre; ++q) {
+    const int e = t + nthr * q;
+    pre[q] = (e < n2 * n2) ? qval(block_ptr(0)[e]) : mk<float>(0, 0);
+  }
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int d = 0; d < 9; ++d) {
+    __syncthreads();                                    // the previous block's reads are done
+#pragma unroll
+    for (int q = 0; q < kMfmaPre; ++q) {
+      const int e = t + nthr * q;
+      if (e < n2 * n2) blk[(e / n2) * ld + e % n2] = pre[q];
+    }
+    for (int e = t; e < kMfmaRhs * n2; e += nthr) {
+      const int k = e / n2, j = e - k * n2;
+      xs[j * ldx + k] = (k < kc) ? xin[((long long)(k0 + k) * cg.nA + nb[d]) * n2 + j] : mk<float>(0, 0);
+    }
+    __syncthreads();
+    if (d + 1 < 9) {
+      const QT *M = block_ptr(d + 1);
+#pragma unroll
+      for (int q = 0; q < kMfmaPre; ++q) {
+        const int e = t + nthr * q;
+        pre[q] = (e < n2 * n2) ? qval(M[e]) : mk<float>(0, 0);
+      }
+    }
+    const bool back = d >= 5;
+    for (int sstep = 0; sstep < n2 / 2; ++sstep) {
+      const int cj = 2 * sstep + (kq >> 1);
+      const c64 m = back ? blk[cj * ld + ci] : blk[ci * ld + cj];
+      const float im = back ? -m.im : m.im;              // Im of the (i, j) entry
+      const float a = (ri == kj) ? m.re : (ri ? im : -im);
+      const c64 xv = xs[cj * ldx + col];
+      const float b = kj ? xv.im : xv.re;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+  }
+  // lane holds complex rows 8w + 2 (l / 16) + h, h = 0, 1, of column col
+  if (col < kc) {
+    const float sg = (float)(dsig ? dsig[k0 + col] : sig.s[k0 + col]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int crow = 8 * w + 2 * kq + h;
+      const long long off = ((long long)(k0 + col) * cg.nA + A) * n2 + crow;
+      c64 v = mk<float>(acc[2 * h], acc[2 * h + 1]) - sg * xin[off];
+      if (g5form && crow >= n2 / 2) v = -v;
+      yout[off] = v;
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T> *__restrict__ y, long long n) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,8 +277,14 @@ __global__ void k_set_shifts(Shifts s, int n, double *dst) {
 // Variants of the coarse apply: 0 = one wave per (site, rhs); 1..3 = one
 // workgroup per site with the blocks staged in LDS for 4, 8 or 16 rhs per pass;
 // 4, 5 = as 1, 2 with one workgroup per (site, chunk of 4 or 8 rhs), for
-// coarse grids too small to fill the GPU with one workgroup per site.
-constexpr int kCoarseVariants = 6;
+// coarse grids too small to fill the GPU with one workgroup per site; 6 = the
+// matrix-core kernel (FP32 arithmetic only, 2Nv a multiple of 8 up to 64).
+constexpr int kCoarseVariants = 7;
+constexpr int kCoarseMfma = 6;
+
+template <typename T> bool mfma_applies(const CoarseGeom &cg) {
+  return sizeof(T) == 4 && cg.n2 % 8 == 0 && cg.n2 <= kMfmaMaxN2;
+}
 
 template <typename T, typename QT>
 void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const QT *Qc, const cplx<T> *x,
@@ -208,6 +309,18 @@ void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const Q
     case 5:
       LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 8>), dim3(cg.nA, (nrhs + 7) / 8), dim3(256), 0, st, cg, Qc, x, y,
                 sig, dsig, g5form, nrhs);
+      break;
+    case kCoarseMfma:
+      if constexpr (std::is_same<T, float>::value) {
+        if (mfma_applies<T>(cg)) {
+          LQ_LAUNCH(kt, (k_coarse_apply_mfma<QT>), dim3(cg.nA, (nrhs + kMfmaRhs - 1) / kMfmaRhs),
+                    dim3(64 * (cg.n2 / 8)), 0, st, cg, Qc, x, y, sig, dsig, g5form, nrhs);
+          break;
+        }
+      }
+      // not applicable to this precision or block size: the LDS kernel for 8 rhs
+      LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 8>), dim3(cg.nA), dim3(256), 0, st, cg, Qc, x, y, sig, dsig, g5form,
+                nrhs);
       break;
     default:
       LQ_LAUNCH(kt, (k_coarse_apply<T, QT>), dim3(cg.nA, nrhs), dim3(64), 0, st, cg, Qc, x, y, sig, dsig, g5form);
@@ -280,6 +393,7 @@ int tune_coarse_apply_q(const CoarseGeom &cg, const QT *Qc, const cplx<T> *x, cp
   int best = 0;
   float tbest = 1e30f;
   for (int v = 0; v < kCoarseVariants; ++v) {
+    if (v == kCoarseMfma && !mfma_applies<T>(cg)) continue;
     coarse_launch_variant<T, QT>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
     LQ_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 3; ++r) coarse_launch_variant<T, QT>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);

@@ -448,7 +448,7 @@ def kernel_timer_read():
 
 
 def coarse_variant(v: int) -> None:
-    """Force coarse-apply kernel v (0..5) for every shape, or -1 for the tuned choice."""
+    """Force coarse-apply kernel v (0..6; 6 = matrix cores) for every shape, or -1 for the tuned choice."""
     rc = load().lq_coarse_variant(int(v))
     if rc != 0:
         raise LQError(rc, f"lq_coarse_variant({v}) failed")

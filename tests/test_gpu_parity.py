@@ -293,7 +293,7 @@ def coarse_kernel():
     coarse_variant(-1)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("prec,tol,bf16", [(0, 1e-12, 0), (1, 3e-6, 0), (1, 1e-2, 1)], ids=["fp64", "fp32", "bf16"])
 def test_coarse_apply_many_sites(prec, tol, bf16, variant, coarse_kernel):
     # 8192 coarse sites, each of the six coarse-apply kernels (one wave per
@@ -325,22 +325,25 @@ def test_coarse_apply_many_sites(prec, tol, bf16, variant, coarse_kernel):
         assert relmax(y, ref) > 1e-5          # the bfloat16 operator was the one applied
 
 
-def test_coarse_apply_galerkin_identity_full_blocks():
-    # 4096 coarse sites with 48 x 48 blocks (Nv = 24, the benchmark's block
-    # size), mixed precision: the coarse apply equals P^dag (Q - sigma) P x,
-    # the Galerkin identity of sec. 2, formed from the prolongation, the FP64
-    # Q apply and the restriction (each pinned to the oracle on small cases).
+@pytest.mark.parametrize("nv,variant", [(24, -1), (24, 6), (32, 6)], ids=["48-tuned", "48-mfma", "64-mfma"])
+def test_coarse_apply_galerkin_identity_full_blocks(nv, variant, coarse_kernel):
+    # 4096 coarse sites with 48 x 48 blocks (Nv = 24) or 64 x 64 (Nv = 32, the
+    # 32^3 x 64 workload's), mixed precision, the tuned kernel or the
+    # matrix-core one: the coarse apply equals P^dag (Q - sigma) P x, the
+    # Galerkin identity of sec. 2, formed from the prolongation, the FP64 Q
+    # apply and the restriction (each pinned to the oracle on small cases).
+    coarse_kernel(variant)
     dims, agg = (16, 16, 16, 16), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 41)
     from paper_1509_06865_amd import MGParams
     c = _ctx(dims, 1)
     Ud = dev(U)
-    c.mg_setup(Ud, -0.15, agg, dev(lqsynth.gaussian_spinors(24, dims, 42)),
+    c.mg_setup(Ud, -0.15, agg, dev(lqsynth.gaussian_spinors(nv, dims, 42)),
                MGParams(precision=1, n_setup=0, n_init=1))
     nA = 8 ** 3 * 8
     rng = np.random.default_rng(43)
     nr = 9
-    x = rng.standard_normal((nr, nA, 48)) + 1j * rng.standard_normal((nr, nA, 48))
+    x = rng.standard_normal((nr, nA, 2 * nv)) + 1j * rng.standard_normal((nr, nA, 2 * nv))
     sig = [0.03 * k - 0.1 for k in range(nr)]
     y = host(c.coarse_apply(sig, dev(x)))
     for k in (0, 4, 8):
