@@ -348,6 +348,9 @@ def main():
     ap.add_argument("--n-eig", type=int, default=None, help="override the workload's eigenpair count")
     ap.add_argument("--guard", type=int, default=None)
     ap.add_argument("--nv", type=int, default=None)
+    ap.add_argument("--levels", type=int, default=None, choices=(2, 3),
+                    help="2 = drop the workload's third level; 3 = add one (aggregates 2^4 of the coarse lattice)")
+    ap.add_argument("--nv2", type=int, default=None)
     ap.add_argument("--max-sweeps", type=int, default=40)
     ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
     ap.add_argument("--kernel-only", action="store_true",
@@ -386,9 +389,15 @@ def main():
 
     wl = dict(WORKLOADS[args.workload])
     wl["params"] = dict(wl["params"])
-    for key in ("n_eig", "guard", "nv"):
+    for key in ("n_eig", "guard", "nv", "nv2"):
         if getattr(args, key) is not None:
             wl[key] = getattr(args, key)
+    if args.levels == 2:
+        wl.pop("agg2", None)
+        wl.pop("nv2", None)
+    elif args.levels == 3 and not wl.get("agg2"):
+        wl["agg2"] = (2, 2, 2, 2)
+        wl.setdefault("nv2", min(24, wl["nv"]))
     for kv in args.param:
         k, v = kv.split("=")
         wl["params"][k] = float(v) if ("." in v or "e" in v) else int(v)
@@ -417,7 +426,7 @@ def main():
     log(f"q_apply FP64 {t64 * 1e3:.3f} ms = {gbs64:.0f} GB/s ; FP32 {t32 * 1e3:.3f} ms = {gbs32:.0f} GB/s")
 
     def step():
-        ctx.mg_setup(U, m0, wl["agg"], tv0, prm)
+        ctx.mg_setup(U, m0, wl["agg"], tv0, prm, agg2=wl.get("agg2"), nv2=wl.get("nv2"))
         t_setup = time.time()
         free, total = torch.cuda.mem_get_info()
         log(f"after setup: device free {free / 2**30:.1f} GiB, torch reserved "
@@ -454,8 +463,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(1e3 * T, 1), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 (RQI, FGMRES) + f32 (multigrid)", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} t_bc={t_bc} eps={eps} "
-                               f"m0={m0}, 2-level MG {wl['agg']} aggregates Nv={wl['nv']}, lowest {wl['n_eig']} "
-                               f"eigenpairs at residual {wl['tol']}",
+                               f"m0={m0}, " + (f"3-level MG {wl['agg']} / {wl['agg2']} aggregates "
+                                               f"Nv={wl['nv']}/{wl['nv2']}" if wl.get("agg2") else
+                                               f"2-level MG {wl['agg']} aggregates Nv={wl['nv']}") +
+                               f", lowest {wl['n_eig']} eigenpairs at residual {wl['tol']}",
                    "n_eig": wl["n_eig"], "tol": wl["tol"], "converged": info["converged"],
                    "smallest_abs_lambda": float(abs(lam[0])), "largest_abs_lambda": float(abs(lam[-1])),
                    "max_residual": float(max(res)), "setup_s": round(max(setups), 3),
@@ -476,7 +487,7 @@ def main():
                          **wl["params"])
         torch.cuda.synchronize()
         a = time.time()
-        ctx.mg_setup(U, m0, wl["agg"], tv0, prm64)
+        ctx.mg_setup(U, m0, wl["agg"], tv0, prm64, agg2=wl.get("agg2"), nv2=wl.get("nv2"))
         lam64, _, res64, info64 = ctx.rqi_lowmodes(wl["n_eig"], wl["tol"], V0=V0)
         torch.cuda.synchronize()
         t64p = time.time() - a

@@ -98,6 +98,14 @@ typedef struct {
                            and accumulation): half the coarse operator's bytes,
                            a coarse operator accurate to ~2^-9 relative; the FP64
                            outer FGMRES keeps the solves exact.  0 = FP32 Q_c */
+  /* three-level hierarchies only (n_levels = 3 in mg_setup): the level-1
+     system is then solved by FGMRES (coarse_m, coarse_restarts, coarse_tol
+     above) right-preconditioned by a level-1 two-grid cycle made of */
+  int coarse2_m;        /* the level-2 GMRES (on the gamma5^c2 form): restart length */
+  int coarse2_restarts; /* its restarts after the first cycle */
+  double coarse2_tol;   /* its relative residual target */
+  int smooth1_m;        /* GMRES steps per level-1 smoothing step (gamma5^c form) */
+  int post1;            /* level-1 post-smoothing steps after the level-2 correction */
 } lq_mg_params;
 
 typedef struct {
@@ -135,20 +143,27 @@ int q_apply(lq_ctx *ctx, const lq_c128 *U, double m0, const lq_c128 *x,
 int q_apply_c64(lq_ctx *ctx, const lq_c64 *U, double m0, const lq_c64 *x,
                 lq_c64 *y, int n_rhs);
 
-/* Adaptive multigrid setup (sec. 2.1) for Q(U, m0).  agg: host int[4] block
- * extents of the aggregates (each divides the lattice extent; the number of
- * blocks per direction is 1 or even, so that red/black SAP is well defined);
- * n_tv: number Nv of test vectors (2*Nv coarse unknowns per aggregate,
- * 1 <= Nv <= min(32, 6*prod(agg))).  tv0: device [n_tv][12][V] random start
- * vectors (the method draws no random numbers itself).  p: NULL = defaults.
- * Copies U; replaces any previous hierarchy.  After an error the context holds
- * no hierarchy (solve and RQI calls return LQ_ERR_STATE until a setup succeeds).
- * Start vectors that are linearly dependent on an aggregate are an error; if
- * the setup's multigrid passes make them so, those aggregates keep their
- * previous interpolation columns.
+/* Adaptive multigrid setup (sec. 2.1) for Q(U, m0) with n_levels = 2 (the
+ * paper's hierarchy) or 3 levels.  agg: host int[n_levels - 1][4]; agg[0] =
+ * block extents of the fine aggregates (each divides the lattice extent; the
+ * number of blocks per direction is 1 or even, so that red/black SAP is well
+ * defined; at most 256 sites); agg[1] (three levels) = block extents of the
+ * level-2 aggregates on the lattice of aggregates (each divides its extent).
+ * n_tv: host int[n_levels - 1]; n_tv[0] = Nv test vectors (2*Nv coarse
+ * unknowns per aggregate, 1 <= Nv <= min(32, 6*prod(agg[0]))); n_tv[1] = Nv2
+ * of the third level (1 <= Nv2 <= min(32, Nv)): the level-2 test vectors are
+ * the restrictions P^dag w of the first Nv2 vectors that build P (during RQI
+ * the eigenvector approximations), orthonormalised per level-2 aggregate and
+ * gamma5^c half.  tv0: device [n_tv[0]][12][V] random start vectors (the
+ * method draws no random numbers itself).  p: NULL = defaults.  Copies U;
+ * replaces any previous hierarchy.  After an error the context holds no
+ * hierarchy (solve and RQI calls return LQ_ERR_STATE until a setup succeeds).
+ * Start vectors that are linearly dependent on an aggregate (or level-2
+ * aggregate) are an error; if the setup's multigrid passes make them so,
+ * those aggregates keep their previous interpolation columns.
  * Errors: LQ_ERR_ARG, LQ_ERR_OOM, LQ_ERR_NUMERIC (locally dependent start vectors). */
-int mg_setup(lq_ctx *ctx, const lq_c128 *U, double m0, const int agg[4],
-             int n_tv, const lq_c128 *tv0, const lq_mg_params *p);
+int mg_setup(lq_ctx *ctx, const lq_c128 *U, double m0, int n_levels, const int n_tv[],
+             const int agg[][4], const lq_c128 *tv0, const lq_mg_params *p);
 
 /* Solve (Q - sigma[k]) x[k] = rhs[k] for k < n_rhs (1..16) to the relative
  * residual tol with FP64 flexible GMRES preconditioned by the multigrid cycle
@@ -318,6 +333,16 @@ int mg_get_interp(lq_ctx *ctx, lq_c128 *P);
  * column index of the neighbour); the A - mu blocks are the conjugate
  * transposes of the A - mu forward blocks (Q_c is Hermitian). */
 int mg_get_coarse(lq_ctx *ctx, lq_c128 *Qc);
+/* Third level: Nv2 and the number nA2 of level-2 aggregates (LQ_ERR_STATE
+ * for a two-level hierarchy). */
+int mg_info2(lq_ctx *ctx, int *nv2, int *n_agg2);
+/* The third level's P2 as Nv2 level-1 vectors, device [Nv2][nA][2Nv] c128
+ * (restricted to level-2 aggregate A2 and gamma5^c half h they give the
+ * orthonormal columns (A2, h, k)), and Q_c2 = P2^dag Q_c P2, device
+ * [nA2][5][2Nv2][2Nv2] c128 in the layout of mg_get_coarse (level-2 lattice:
+ * the lattice of aggregates cut into blocks agg[1], x fastest).  Either may
+ * be NULL.  Errors: LQ_ERR_STATE (two levels). */
+int mg_get_level2(lq_ctx *ctx, lq_c128 *P2, lq_c128 *Qc2);
 /* Restriction c = P^dag f: f device [n][12][V], c device [n][nA][2Nv]. */
 int mg_restrict(lq_ctx *ctx, int n, const lq_c128 *f, lq_c128 *c);
 /* Prolongation f = P c (shapes as above). */

@@ -143,6 +143,32 @@ int coarse_force_variant(int v);
 template <typename T>
 void launch_coarse_g5(const CoarseGeom &cg, const cplx<T> *x, cplx<T> *y, int nrhs, hipStream_t st);
 
+// ---- third level (level2.hip) -----------------------------------------------------
+// The lattice of aggregates (level 1, coarse sites canonical, x fastest) cut
+// into blocks of extent b2 (level-2 aggregates).
+struct Level2Geom {
+  int nb1[4];      // level-1 lattice extents
+  int b2[4];       // level-2 aggregate extents on it
+  int nb2[4];      // level-2 lattice extents
+  int nA1, nA2, bvol2;
+  int Nv1, Nv2;    // test vectors per level (2 Nv unknowns per site)
+};
+// c2[j][A2][h Nv2 + k] = sum_{A1 in A2, c} conj(P2_k[A1][h Nv1 + c]) v_j[A1][h Nv1 + c]
+template <typename T>
+void launch_restrict2(const Level2Geom &g, const cplx<T> *P2, const cplx<T> *v, int nrhs, cplx<T> *c2,
+                      hipStream_t st);
+// v_j (+)= P2 c2_j
+template <typename T>
+void launch_prolong2(const Level2Geom &g, const cplx<T> *P2, const cplx<T> *c2, cplx<T> *v, int nrhs,
+                     bool accumulate, hipStream_t st);
+// P2 from level-1 test vectors W [Nv2][nA1][2 Nv1] (FP64): local CholQR twice per (A2, half);
+// *status raised (block left as it was) where the vectors are dependent
+void launch_build_P2(const Level2Geom &g, const c128 *W, c128 *P2, int *status, hipStream_t st);
+// split couplings of Q_c applied to nc half-columns of P2: parts[q][5][nA1][2 Nv1]
+template <typename T>
+void launch_coarse_parts2(const Level2Geom &g, const cplx<T> *Qc, const cplx<T> *x, const int *half_dev, int nc,
+                          long long xstride, cplx<T> *parts, hipStream_t st);
+
 // ---- parallel-transport convolution (ptc.hip) ---------------------------------
 // out[o] = sum_i sum_d W[o][i][d] T_d phi[i](. + d), canonical layout, FP64;
 // phi [cin][12][V], W [cout][cin][81][4][4], out [cout][12][V]

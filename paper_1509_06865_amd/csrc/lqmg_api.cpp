@@ -78,6 +78,8 @@ template <typename T> struct MGData {
   DevBuf<cplx<T>> U;    // blocked links (T precision)
   DevBuf<cplx<T>> P;    // [Nv][12][V]
   DevBuf<cplx<T>> Qc;   // [nA][5][n2][n2]
+  DevBuf<cplx<T>> P2;   // third level: [Nv2][nA][n2]
+  DevBuf<cplx<T>> Qc2;  // [nA2][5][n22][n22]
 };
 
 // Device-side state of one batched GMRES: Hessenberg columns, Givens
@@ -158,6 +160,19 @@ struct lq_ctx {
   DevBuf<double> coarse_sig;        // shifts of the current coarse solve [kMaxRhs]
   DevBuf<bf16c> QcB;                // the FP32 Q_c in bfloat16 (coarse_bf16)
   DevBuf<double> net_scratch;       // per-site partial sums of the network's bias gradients
+  // third level (n_levels == 3): aggregates of the coarse lattice
+  int n_levels = 2;
+  int Nv2 = 0;
+  int agg2[4] = {1, 1, 1, 1};
+  Level2Geom l2g;
+  CoarseGeom cg2;
+  DevBuf<c128> P2_64, W2;            // level-2 interpolation (FP64) and the level-1 vectors it is built from
+  KrylovWork<double> smooth1_kw64, coarse2_kw64;
+  KrylovWork<float> smooth1_kw32, coarse2_kw32;
+  DevBuf<c128> l1w64, l2w64;         // level-1 / level-2 work vectors (FP64)
+  DevBuf<c64> l1w32, l2w32;          // (FP32)
+  DevBuf<c128> parts2_64, pc2_64;
+  DevBuf<c64> parts2_32, pc2_32;
   int coarse_iters = 0;
   // captured coarse-GMRES chunks, keyed by shape, step range and every pointer
   // they use; cap_st is the private stream they are captured on
@@ -475,46 +490,47 @@ void sap(lq_ctx *c, const double *sig, const cplx<T> *r, cplx<T> *z, int nrhs, i
                              c->p.sap_mr, c->st);
 }
 
+// Restarted GMRES for (Q_c - sigma) e = c on one coarse level (the operator
+// cg / Qc), run on the equivalent gamma5^c form (R16: same solution, a field
+// of values near the right half plane).  QcB: the bfloat16 copy of an FP32
+// operator, or null.  graphs: the Arnoldi chunks may be replayed from
+// captured graphs (direct launches otherwise).
 template <typename T>
-void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, int nrhs, cplx<T> *rhs_buf) {
-  const long long n = (long long)c->cg.nA * c->cg.n2;
+void coarse_gmres(lq_ctx *c, const CoarseGeom &cg, const cplx<T> *Qc, const bf16c *QcB, KrylovWork<T> &kw,
+                  const double *sig, const cplx<T> *rc, cplx<T> *ec, int nrhs, cplx<T> *rhs_buf, int m, int restarts,
+                  double tol, bool graphs_ok) {
+  const long long n = (long long)cg.nA * cg.n2;
   Shifts S = shifts_of(sig, nrhs);
-  launch_coarse_g5<T>(c->cg, rc, rhs_buf, nrhs, c->st);
+  launch_coarse_g5<T>(cg, rc, rhs_buf, nrhs, c->st);
   // graphs only while the coarse apply is not being timed (its timed launch
   // records events, which a capture cannot hold).  With graphs the shifts go
   // to device memory, so the coarse-apply launches are the same for every
   // solve of this shape and the captured steps can be replayed.
-  const bool graphs = c->p.graphs && g_ktimer_class != KT_COARSE;
+  const bool graphs = graphs_ok && c->p.graphs && g_ktimer_class != KT_COARSE;
   double *dsig = nullptr;
   if (graphs) {
     dsig = c->coarse_sig.get(kMaxRhs);
     launch_set_shifts(S, nrhs, dsig, c->st);
   }
   KOps<T> ops;
-  const cplx<T> *Qc = mgd<T>(c).Qc.p;
-  // the FP32 cycle may read Q_c from its bfloat16 copy (FP32 arithmetic)
-  const bf16c *QcB = nullptr;
-  if constexpr (std::is_same<T, float>::value)
-    if (c->p.coarse_bf16) QcB = c->QcB.p;
   auto capply = [=](const cplx<T> *x, cplx<T> *y) {
     if constexpr (std::is_same<T, float>::value) {
       if (QcB) {
-        launch_coarse_apply_bf16(c->cg, QcB, x, y, S, nrhs, true, c->st, dsig);
+        launch_coarse_apply_bf16(cg, QcB, x, y, S, nrhs, true, c->st, dsig);
         return;
       }
     }
-    launch_coarse_apply<T>(c->cg, Qc, x, y, S, nrhs, true, c->st, dsig);
+    launch_coarse_apply<T>(cg, Qc, x, y, S, nrhs, true, c->st, dsig);
   };
   // kernel variant for this shape: timed once, before any capture (ec is
   // overwritten here and zeroed by GMRES)
   int variant;
   if constexpr (std::is_same<T, float>::value)
-    variant = QcB ? tune_coarse_apply_bf16(c->cg, QcB, rhs_buf, ec, nrhs, c->st)
-                  : tune_coarse_apply<T>(c->cg, Qc, rhs_buf, ec, nrhs, c->st);
+    variant = QcB ? tune_coarse_apply_bf16(cg, QcB, rhs_buf, ec, nrhs, c->st)
+                  : tune_coarse_apply<T>(cg, Qc, rhs_buf, ec, nrhs, c->st);
   else
-    variant = tune_coarse_apply<T>(c->cg, Qc, rhs_buf, ec, nrhs, c->st);
+    variant = tune_coarse_apply<T>(cg, Qc, rhs_buf, ec, nrhs, c->st);
   ops.apply = capply;
-  auto &kw = ckw<T>(c);
   const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
   ops.resid = [=](const cplx<T> *b, const cplx<T> *x, cplx<T> *r) {
     capply(x, r);
@@ -525,12 +541,95 @@ void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, 
   // every by-value argument of the captured launches belongs to the key: the
   // coarse lattice extents too (two aggregate shapes with equal nA and n2 must
   // not share a graph)
-  const std::vector<uint64_t> gid = {QcB ? key_bits(QcB) : key_bits(Qc), key_bits(dsig), (uint64_t)c->cg.nA,
-                                     (uint64_t)c->cg.n2, (uint64_t)c->cg.nb[0], (uint64_t)c->cg.nb[1],
-                                     (uint64_t)c->cg.nb[2], (uint64_t)c->cg.nb[3],
+  const std::vector<uint64_t> gid = {QcB ? key_bits(QcB) : key_bits(Qc), key_bits(dsig), (uint64_t)cg.nA,
+                                     (uint64_t)cg.n2, (uint64_t)cg.nb[0], (uint64_t)cg.nb[1],
+                                     (uint64_t)cg.nb[2], (uint64_t)cg.nb[3],
                                      (uint64_t)variant, key_bits(pm1)};
-  gmres_batched<T>(c, kw, n, nrhs, ops, rhs_buf, ec, c->p.coarse_m, c->p.coarse_restarts, c->p.coarse_tol, its,
-                   nullptr, 8, graphs ? &gid : nullptr);
+  gmres_batched<T>(c, kw, n, nrhs, ops, rhs_buf, ec, m, restarts, tol, its, nullptr, 8, graphs ? &gid : nullptr);
+  for (int k = 0; k < nrhs; ++k) c->coarse_iters += its[k];
+}
+
+template <typename T> KrylovWork<T> &s1kw(lq_ctx *c);
+template <> KrylovWork<double> &s1kw<double>(lq_ctx *c) { return c->smooth1_kw64; }
+template <> KrylovWork<float> &s1kw<float>(lq_ctx *c) { return c->smooth1_kw32; }
+template <typename T> KrylovWork<T> &c2kw(lq_ctx *c);
+template <> KrylovWork<double> &c2kw<double>(lq_ctx *c) { return c->coarse2_kw64; }
+template <> KrylovWork<float> &c2kw<float>(lq_ctx *c) { return c->coarse2_kw32; }
+template <typename T> cplx<T> *l1work(lq_ctx *c, size_t n);
+template <> c128 *l1work<double>(lq_ctx *c, size_t n) { return c->l1w64.get(n); }
+template <> c64 *l1work<float>(lq_ctx *c, size_t n) { return c->l1w32.get(n); }
+template <typename T> cplx<T> *l2work(lq_ctx *c, size_t n);
+template <> c128 *l2work<double>(lq_ctx *c, size_t n) { return c->l2w64.get(n); }
+template <> c64 *l2work<float>(lq_ctx *c, size_t n) { return c->l2w32.get(n); }
+
+// The level-1 two-grid cycle B1 ~ (Q_c - sigma)^{-1} of the three-level
+// hierarchy: the level-2 correction P2 (Q_c2 - sigma)^{-1} P2^dag r (GMRES to
+// coarse2_tol), then post1 smoothing steps, each smooth1_m GMRES steps on
+// gamma5^c (Q_c - sigma) for the current residual.
+template <typename T>
+void cycle1(lq_ctx *c, const double *sig, const cplx<T> *r1, cplx<T> *z1, int nrhs) {
+  const long long n1 = (long long)c->cg.nA * c->cg.n2, n2 = (long long)c->cg2.nA * c->cg2.n2;
+  auto &d = mgd<T>(c);
+  Shifts S = shifts_of(sig, nrhs);
+  cplx<T> *w2 = l2work<T>(c, (size_t)3 * kMaxRhs * n2);
+  cplx<T> *r2 = w2, *e2 = w2 + kMaxRhs * n2, *b2 = w2 + 2 * kMaxRhs * n2;
+  cplx<T> *w1 = l1work<T>(c, (size_t)3 * kMaxRhs * n1);
+  cplx<T> *t1 = w1, *g1 = w1 + kMaxRhs * n1, *d1 = w1 + 2 * kMaxRhs * n1;
+  launch_restrict2<T>(c->l2g, d.P2.p, r1, nrhs, r2, c->st);
+  coarse_gmres<T>(c, c->cg2, d.Qc2.p, nullptr, c2kw<T>(c), sig, r2, e2, nrhs, b2, c->p.coarse2_m,
+                  c->p.coarse2_restarts, c->p.coarse2_tol, false);
+  launch_prolong2<T>(c->l2g, d.P2.p, e2, z1, nrhs, false, c->st);
+  const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
+  for (int step = 0; step < c->p.post1; ++step) {
+    // g1 = gamma5^c (r1 - (Q_c - sigma) z1)
+    launch_coarse_apply<T>(c->cg, d.Qc.p, z1, t1, S, nrhs, false, c->st);
+    launch_scale<T>(pm1, t1, n1, t1, n1, n1, nrhs, false, c->st);
+    launch_multi_axpy<T>(1, r1, 0, n1, pp1, t1, n1, n1, nrhs, 1.0, c->st);
+    launch_coarse_g5<T>(c->cg, t1, g1, nrhs, c->st);
+    KOps<T> ops;
+    const CoarseGeom cg = c->cg;
+    const cplx<T> *Qc = d.Qc.p;
+    ops.apply = [=](const cplx<T> *x, cplx<T> *y) { launch_coarse_apply<T>(cg, Qc, x, y, S, nrhs, true, c->st); };
+    ops.resid = [=](const cplx<T> *b, const cplx<T> *x, cplx<T> *r) {
+      launch_coarse_apply<T>(cg, Qc, x, r, S, nrhs, true, c->st);
+      launch_scale<T>(pm1, r, n1, r, n1, n1, nrhs, false, c->st);
+      launch_multi_axpy<T>(1, b, 0, n1, pp1, r, n1, n1, nrhs, 1.0, c->st);
+    };
+    gmres_batched<T>(c, s1kw<T>(c), n1, nrhs, ops, g1, d1, c->p.smooth1_m, 0, 0.0, nullptr, nullptr, 0);
+    launch_multi_axpy<T>(1, d1, 0, n1, pp1, z1, n1, n1, nrhs, 1.0, c->st);
+  }
+}
+
+// The coarse solve of the cycle: two levels, restarted GMRES on Q_c; three
+// levels, FGMRES on Q_c - sigma right-preconditioned by the level-1 cycle.
+template <typename T>
+void coarse_solve(lq_ctx *c, const double *sig, const cplx<T> *rc, cplx<T> *ec, int nrhs, cplx<T> *rhs_buf) {
+  const cplx<T> *Qc = mgd<T>(c).Qc.p;
+  if (c->n_levels == 2) {
+    // the FP32 cycle may read Q_c from its bfloat16 copy (FP32 arithmetic)
+    const bf16c *QcB = nullptr;
+    if constexpr (std::is_same<T, float>::value)
+      if (c->p.coarse_bf16) QcB = c->QcB.p;
+    coarse_gmres<T>(c, c->cg, Qc, QcB, ckw<T>(c), sig, rc, ec, nrhs, rhs_buf, c->p.coarse_m, c->p.coarse_restarts,
+                    c->p.coarse_tol, true);
+    return;
+  }
+  const long long n1 = (long long)c->cg.nA * c->cg.n2;
+  Shifts S = shifts_of(sig, nrhs);
+  std::vector<double> sv(sig, sig + nrhs);
+  const CoarseGeom cg = c->cg;
+  const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
+  KOps<T> ops;
+  ops.apply = [=](const cplx<T> *x, cplx<T> *y) { launch_coarse_apply<T>(cg, Qc, x, y, S, nrhs, false, c->st); };
+  ops.precond = [=](const cplx<T> *v, cplx<T> *z) { cycle1<T>(c, sv.data(), v, z, nrhs); };
+  ops.resid = [=](const cplx<T> *b, const cplx<T> *x, cplx<T> *r) {
+    launch_coarse_apply<T>(cg, Qc, x, r, S, nrhs, false, c->st);
+    launch_scale<T>(pm1, r, n1, r, n1, n1, nrhs, false, c->st);
+    launch_multi_axpy<T>(1, b, 0, n1, pp1, r, n1, n1, nrhs, 1.0, c->st);
+  };
+  int its[kMaxRhs];
+  gmres_batched<T>(c, ckw<T>(c), n1, nrhs, ops, rc, ec, c->p.coarse_m, c->p.coarse_restarts, c->p.coarse_tol, its,
+                   nullptr, 1);
   for (int k = 0; k < nrhs; ++k) c->coarse_iters += its[k];
 }
 
@@ -618,6 +717,63 @@ template <typename T> void build_coarse(lq_ctx *c, DevBuf<cplx<T>> &parts, DevBu
     }
 }
 
+// Q_c2 = P2^dag Q_c P2 in precision T from P2_T and Q_c (T): the split
+// couplings of Q_c applied to each half-column of P2, restricted, scattered.
+template <typename T> void build_coarse2(lq_ctx *c, DevBuf<cplx<T>> &parts, DevBuf<cplx<T>> &pc) {
+  auto &d = mgd<T>(c);
+  const int Nv2 = c->Nv2, n22 = 2 * Nv2, nA2 = c->cg2.nA;
+  const long long n1 = (long long)c->cg.nA * c->cg.n2;
+  const int C = std::min(Nv2, 3);          // 5 C <= 16 restricted parts per pass
+  cplx<T> *pa = parts.get((size_t)C * 5 * n1);
+  cplx<T> *pcb = pc.get((size_t)C * 5 * nA2 * n22);
+  cplx<T> *Qc2 = d.Qc2.get((size_t)nA2 * 5 * n22 * n22);
+  int *dint = c->ints.get(2 * C);
+  for (int h = 0; h < 2; ++h)
+    for (int l0 = 0; l0 < Nv2; l0 += C) {
+      const int nc = std::min(C, Nv2 - l0);
+      std::vector<int> hi(2 * C);
+      for (int j = 0; j < nc; ++j) { hi[j] = h; hi[C + j] = h * Nv2 + l0 + j; }
+      LQ_HIP(hipMemcpyAsync(dint, hi.data(), 2 * C * sizeof(int), hipMemcpyHostToDevice, c->st));
+      launch_coarse_parts2<T>(c->l2g, d.Qc.p, d.P2.p + l0 * n1, dint, nc, n1, pa, c->st);
+      launch_restrict2<T>(c->l2g, d.P2.p, pa, 5 * nc, pcb, c->st);
+      launch_scatter_coarse<T>(pcb, nc, dint + C, n22, nA2, Qc2, c->st);
+      sync(c);
+    }
+}
+
+// The third level from the first Nv2 of the fields src (blocked FP64) that
+// built P: their restrictions P^dag src are the level-1 test vectors of P2
+// (the level-1 images of the approximations, as the fine vectors are for P).
+// Dependence on a level-2 aggregate half: an error, or with keep_dependent
+// that block of P2 keeps its previous columns (returns false).
+bool rebuild2(lq_ctx *c, const c128 *src, bool keep_dependent) {
+  const long long V12 = 12LL * c->g.V, n1 = (long long)c->cg.nA * c->cg.n2;
+  const size_t nP2 = (size_t)c->Nv2 * n1;
+  c128 *W2 = c->W2.get(nP2);
+  // restriction with the FP64 P, at most 16 fields per launch
+  for (int k0 = 0; k0 < c->Nv2; k0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, c->Nv2 - k0);
+    launch_restrict<double>(c->g, c->P64.p, c->Nv, src + k0 * V12, V12, nk, W2 + k0 * n1, c->st);
+  }
+  int *st = c->status.get(1);
+  LQ_HIP(hipMemsetAsync(st, 0, sizeof(int), c->st));
+  c128 *P2 = c->P2_64.get(nP2);
+  launch_build_P2(c->l2g, W2, P2, st, c->st);
+  int h_st = 0;
+  LQ_HIP(hipMemcpyAsync(&h_st, st, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  sync(c);
+  if (h_st && !keep_dependent) fail(LQ_ERR_NUMERIC, "level-1 test vectors are linearly dependent on a level-2 aggregate");
+  if (c->p.precision == LQ_PREC_FP64) {
+    copy<double>(c, c->d64.P2.get(nP2), P2, nP2);
+    build_coarse2<double>(c, c->parts2_64, c->pc2_64);
+  } else {
+    launch_convert<float, double>(P2, c->d32.P2.get(nP2), (long long)nP2, c->st);
+    build_coarse2<float>(c, c->parts2_32, c->pc2_32);
+  }
+  sync(c);
+  return h_st == 0;
+}
+
 // P and Q_c from the FP64 fields src [Nv][12][V] (blocked).  Fields that are
 // linearly dependent on some aggregate half are an error, unless keep_dependent:
 // then those blocks of P keep their previous columns (the other blocks are
@@ -644,7 +800,9 @@ bool rebuild(lq_ctx *c, const c128 *src, bool keep_dependent = false) {
     }
   }
   sync(c);
-  return h_st == 0;
+  bool ok2 = true;
+  if (c->n_levels == 3) ok2 = rebuild2(c, src, keep_dependent);
+  return h_st == 0 && ok2;
 }
 
 // Gram-Schmidt (twice) of n fields in place, in index order; FP64.
@@ -1095,6 +1253,11 @@ int lq_params_default(lq_mg_params *p) {
   p->rqi_start_passes = 0;
   p->graphs = 0;       // measured: replay gains nothing over direct launches here
   p->coarse_bf16 = 0;
+  p->coarse2_m = 40;
+  p->coarse2_restarts = 2;
+  p->coarse2_tol = 0.1;
+  p->smooth1_m = 4;
+  p->post1 = 1;
   return LQ_OK;
 }
 
@@ -1167,14 +1330,17 @@ int q_apply_c64(lq_ctx *c, const lq_c64 *U, double m0, const lq_c64 *x, lq_c64 *
   });
 }
 
-int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv, const lq_c128 *tv0,
-             const lq_mg_params *prm) {
+int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, int n_levels, const int n_tvs[], const int aggs[][4],
+             const lq_c128 *tv0, const lq_mg_params *prm) {
   return guard(c, [&] {
     check_ctx(c);
     c->have = false;                     // a failed setup leaves no usable hierarchy
     // graphs captured for the previous hierarchy refer to its buffers and shapes
     drop_graphs(c);
-    if (!U || !agg || !tv0) fail(LQ_ERR_ARG, "mg_setup: NULL pointer");
+    if (!U || !aggs || !n_tvs || !tv0) fail(LQ_ERR_ARG, "mg_setup: NULL pointer");
+    if (n_levels != 2 && n_levels != 3) fail(LQ_ERR_ARG, "mg_setup: n_levels must be 2 or 3");
+    const int *agg = aggs[0];
+    const int n_tv = n_tvs[0];
     int bvol = 1;
     for (int m = 0; m < 4; ++m) {
       if (agg[m] < 1 || c->L[m] % agg[m]) fail(LQ_ERR_ARG, "aggregate extent does not divide the lattice");
@@ -1205,6 +1371,36 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, const int agg[4], int n_tv,
     for (int m = 0; m < 4; ++m) c->cg.nb[m] = c->g.nb[m];
     c->cg.nA = c->g.nblk;
     c->cg.n2 = 2 * n_tv;
+    c->n_levels = n_levels;
+    if (n_levels == 3) {
+      const int *agg2 = aggs[1];
+      const int nv2 = n_tvs[1];
+      if (p.coarse2_m < 1 || p.coarse2_restarts < 0 || p.smooth1_m < 1 || p.post1 < 0)
+        fail(LQ_ERR_ARG, "bad level-2 iteration parameters");
+      Level2Geom &l2 = c->l2g;
+      l2.bvol2 = 1;
+      l2.nA2 = 1;
+      for (int m = 0; m < 4; ++m) {
+        if (agg2[m] < 1 || c->cg.nb[m] % agg2[m]) fail(LQ_ERR_ARG, "level-2 aggregate extent does not divide the "
+                                                                   "lattice of aggregates");
+        l2.nb1[m] = c->cg.nb[m];
+        l2.b2[m] = agg2[m];
+        l2.nb2[m] = c->cg.nb[m] / agg2[m];
+        l2.bvol2 *= agg2[m];
+        l2.nA2 *= l2.nb2[m];
+        c->agg2[m] = agg2[m];
+        c->cg2.nb[m] = l2.nb2[m];
+      }
+      if (nv2 < 1 || nv2 > 32 || nv2 > n_tv) fail(LQ_ERR_ARG, "need 1 <= n_tv[1] <= min(32, n_tv[0])");
+      l2.nA1 = c->cg.nA;
+      l2.Nv1 = n_tv;
+      l2.Nv2 = nv2;
+      c->Nv2 = nv2;
+      c->cg2.nA = l2.nA2;
+      c->cg2.n2 = 2 * nv2;
+    } else {
+      c->Nv2 = 0;
+    }
     const long long V = c->g.V, V12 = 12LL * V;
     // links
     launch_pack_links<double>(c->g, (const c128 *)U, c->U64.get(36 * V), c->st);
@@ -1741,6 +1937,31 @@ int mg_info(lq_ctx *c, int *nv, int *n_agg) {
     need_mg(c);
     if (nv) *nv = c->Nv;
     if (n_agg) *n_agg = c->cg.nA;
+    return LQ_OK;
+  });
+}
+
+int mg_info2(lq_ctx *c, int *nv2, int *n_agg2) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (c->n_levels != 3) fail(LQ_ERR_STATE, "the hierarchy has two levels");
+    if (nv2) *nv2 = c->Nv2;
+    if (n_agg2) *n_agg2 = c->cg2.nA;
+    return LQ_OK;
+  });
+}
+
+int mg_get_level2(lq_ctx *c, lq_c128 *P2, lq_c128 *Qc2) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (c->n_levels != 3) fail(LQ_ERR_STATE, "the hierarchy has two levels");
+    if (P2) copy<double>(c, (c128 *)P2, c->P2_64.p, (size_t)c->Nv2 * c->cg.nA * c->cg.n2);
+    if (Qc2) {
+      const size_t n = (size_t)c->cg2.nA * 5 * c->cg2.n2 * c->cg2.n2;
+      if (c->p.precision == LQ_PREC_FP64) copy<double>(c, (c128 *)Qc2, c->d64.Qc2.p, n);
+      else launch_convert<double, float>(c->d32.Qc2.p, (c128 *)Qc2, (long long)n, c->st);
+    }
+    sync(c);
     return LQ_OK;
   });
 }

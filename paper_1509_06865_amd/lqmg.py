@@ -24,7 +24,8 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "mg_setup", "mg_solve_shifted", "rqi_lowmodes", "mg_info", "mg_get_interp", "mg_get_coarse",
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
-            "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc"]
+            "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc", "mg_info2",
+            "mg_get_level2"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -44,7 +45,8 @@ class _Params(C.Structure):
                 ("rqi_block", C.c_int), ("rqi_max_sweeps", C.c_int), ("rqi_solve_tol", C.c_double),
                 ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int), ("rqi_solve_restarts", C.c_int),
                 ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int), ("graphs", C.c_int),
-                ("coarse_bf16", C.c_int)]
+                ("coarse_bf16", C.c_int), ("coarse2_m", C.c_int), ("coarse2_restarts", C.c_int),
+                ("coarse2_tol", C.c_double), ("smooth1_m", C.c_int), ("post1", C.c_int)]
 
 
 class _SolveStats(C.Structure):
@@ -83,6 +85,11 @@ class MGParams:
     rqi_start_passes: int | None = None
     graphs: int | None = None
     coarse_bf16: int | None = None
+    coarse2_m: int | None = None
+    coarse2_restarts: int | None = None
+    coarse2_tol: float | None = None
+    smooth1_m: int | None = None
+    post1: int | None = None
 
     def to_c(self, lib) -> _Params:
         p = _Params()
@@ -115,7 +122,9 @@ def load():
         "lq_last_error": (C.c_char_p, [vp]),
         "q_apply": (i, [vp, vp, d, vp, vp, i]),
         "q_apply_c64": (i, [vp, vp, d, vp, vp, i]),
-        "mg_setup": (i, [vp, vp, d, ip, i, vp, C.POINTER(_Params)]),
+        "mg_setup": (i, [vp, vp, d, i, ip, ip, vp, C.POINTER(_Params)]),
+        "mg_info2": (i, [vp, ip, ip]),
+        "mg_get_level2": (i, [vp, vp, vp]),
         "mg_solve_shifted": (i, [vp, i, dp, vp, vp, d, C.POINTER(_SolveStats)]),
         "rqi_lowmodes": (i, [vp, i, d, dp, vp, dp, vp, i, C.POINTER(_RQIStats)]),
         "mg_info": (i, [vp, ip, ip]),
@@ -341,14 +350,32 @@ class Context:
         return phi
 
     # -- multigrid ------------------------------------------------------------------
-    def mg_setup(self, U, m0, agg, tv0, params: MGParams | None = None):
+    def mg_setup(self, U, m0, agg, tv0, params: MGParams | None = None, agg2=None, nv2=None):
+        """Two levels (aggregates agg, Nv = tv0.shape[0] test vectors), or three
+        with agg2 (blocks of the lattice of aggregates) and nv2 level-2 vectors."""
         p = (params or MGParams()).to_c(self.lib)
-        agg_c = (C.c_int * 4)(*[int(a) for a in agg])
-        self._check(self.lib.mg_setup(self.h, _ptr(U), float(m0), agg_c, int(tv0.shape[0]), _ptr(tv0),
-                                      C.byref(p)))
+        n_levels = 2 if agg2 is None else 3
+        aggs = [list(agg)] + ([list(agg2)] if agg2 is not None else [])
+        agg_c = ((C.c_int * 4) * len(aggs))(*[(C.c_int * 4)(*[int(a) for a in row]) for row in aggs])
+        nvs = [int(tv0.shape[0])] + ([int(nv2)] if agg2 is not None else [])
+        nv_c = (C.c_int * len(nvs))(*nvs)
+        self._check(self.lib.mg_setup(self.h, _ptr(U), float(m0), n_levels, nv_c,
+                                      C.cast(agg_c, C.POINTER(C.c_int)), _ptr(tv0), C.byref(p)))
         nv, na = C.c_int(), C.c_int()
         self._check(self.lib.mg_info(self.h, C.byref(nv), C.byref(na)))
         self.nv, self.n_agg = nv.value, na.value
+        self.n_levels = n_levels
+        self.nv2 = self.n_agg2 = None
+        if n_levels == 3:
+            self._check(self.lib.mg_info2(self.h, C.byref(nv), C.byref(na)))
+            self.nv2, self.n_agg2 = nv.value, na.value
+
+    def get_level2(self):
+        """(P2 [Nv2, nA, 2 Nv], Q_c2 [nA2, 5, 2 Nv2, 2 Nv2]) of a three-level hierarchy (complex128)."""
+        P2 = torch.empty((self.nv2, self.n_agg, 2 * self.nv), dtype=torch.complex128, device="cuda")
+        Qc2 = torch.empty((self.n_agg2, 5, 2 * self.nv2, 2 * self.nv2), dtype=torch.complex128, device="cuda")
+        self._check(self.lib.mg_get_level2(self.h, _ptr(P2), _ptr(Qc2)))
+        return P2, Qc2
 
     def mg_solve_shifted(self, sigma, rhs, tol, out=None):
         n = rhs.shape[0]

@@ -387,6 +387,14 @@ def test_argument_and_state_errors_are_reported():
         c.mg_solve_shifted([], x[:0], 1e-6)
     with pytest.raises(LQError):
         c.rqi_lowmodes(0, 1e-10)
+    # third level: the level-2 aggregate must divide the lattice of
+    # aggregates (2^4 here), Nv2 <= Nv
+    with pytest.raises(LQError):
+        c2.mg_setup(U, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(4, dims, 78)), MGParams(n_setup=0),
+                    agg2=(3, 1, 1, 1), nv2=2)
+    with pytest.raises(LQError):
+        c2.mg_setup(U, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(4, dims, 78)), MGParams(n_setup=0),
+                    agg2=(2, 2, 2, 2), nv2=5)
     # the context stays usable after the errors
     y = host(c.q_apply(U, m0, x))
     ref = WilsonOp(lqsynth.gauge_field(dims, eps, seed), m0, Lattice(dims, bc)).Q(host(x))

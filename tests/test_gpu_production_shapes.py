@@ -289,3 +289,91 @@ def test_learned_setup_layer_at_network_width():
     d_in, d_W = c.ptc_backward(dev(U), dev(phi), dev(W), dev(G))
     assert relmax(host(d_in), gphi.numpy()) < 1e-12
     assert relmax(host(d_W), gW.numpy()) < 1e-11
+
+
+# ------------------------------------------------------------ third level ---
+@pytest.fixture(scope="module", params=[0, 1], ids=["fp64", "mixed"])
+def hier3(request):
+    # 8^4, fine aggregates 2^4 (a 4^4 lattice of aggregates, Nv = 8), level-2
+    # aggregates 2^4 of it (16 level-2 sites, Nv2 = 6); no setup passes, so
+    # P is the local QR factor of the start vectors and the level-2 test
+    # vectors are their restrictions P^dag w_k, k < Nv2
+    from paper_1509_06865_amd import MGParams
+    dims, agg, agg2, nv, nv2, m0 = DIMS8, (2, 2, 2, 2), (2, 2, 2, 2), 8, 6, -0.2
+    print(f"[hier3] 8^4, {agg} / {agg2}, Nv {nv}/{nv2}, precision {request.param}", flush=True)
+    U = lqsynth.gauge_field(dims, 0.3, 171)
+    lat = Lattice(dims, 1)
+    op = WilsonOp(U, m0, lat)
+    tv0 = lqsynth.gaussian_spinors(nv, dims, 172)
+    prm = MGParams(precision=request.param, n_init=0, n_setup=0, post=2, sap_mr=4, coarse_m=60, coarse_tol=1e-10,
+                   coarse_restarts=10, coarse2_m=80, coarse2_tol=1e-11, coarse2_restarts=4, smooth1_m=4, post1=1)
+    c = _ctx(dims, 1)
+    c.mg_setup(dev(U), m0, agg, dev(tv0), prm, agg2=agg2, nv2=nv2)
+    W = M.orthonormalise(tv0)
+    mg = M.ThreeLevel(op, agg, agg2, M.MGParams(pre=0, post=2, n_mr=4, coarse_m=60, coarse_tol=1e-10,
+                                                coarse_restarts=10),
+                      M.Level2Params(post=1, m_smooth=4, coarse_m=80, coarse_tol=1e-11, coarse_restarts=4))
+    mg.P = M.build_P(W, mg.ag)
+    mg.Qc = M.coarse_operator(op, mg.ag, mg.P)
+    mg.set_level2(M.restrict(mg.P, mg.ag, W[:nv2]))
+    return dict(c=c, mg=mg, op=op, dims=dims, nv=nv, nv2=nv2, prec=request.param)
+
+
+def test_three_level_objects_match_oracle(hier3):
+    h = hier3
+    P2, Qc2 = h["c"].get_level2()
+    assert relmax(host(P2), h["mg"].P2) < 1e-12
+    assert relmax(host(Qc2), h["mg"].Qc2[:, :5]) < (1e-12 if h["prec"] == 0 else 3e-6)
+
+
+def test_three_level_cycle_matches_oracle(hier3):
+    # level-1 and level-2 systems solved to 1e-10 / 1e-11 on both sides
+    h = hier3
+    r = lqsynth.gaussian_spinors(2, h["dims"], 173)
+    sig = [0.0, 0.02]
+    z = host(h["c"].cycle(sig, dev(r)))
+    ref = np.stack([h["mg"].cycle(sig[k], r[k]) for k in range(2)])
+    assert relmax(z, ref) < (1e-8 if h["prec"] == 0 else 5e-5)
+
+
+def test_three_level_solve_matches_two_level_solve(hier3):
+    # the same shifted systems to 1e-10 through both hierarchies
+    from paper_1509_06865_amd import MGParams
+    h = hier3
+    U = lqsynth.gauge_field(h["dims"], 0.3, 171)
+    b = lqsynth.gaussian_spinors(3, h["dims"], 174)
+    sig = [0.0, 0.01, -0.02]
+    x3, i3 = h["c"].mg_solve_shifted(sig, dev(b), 1e-10)
+    assert i3["converged"], i3
+    c2 = _ctx(h["dims"], 1)
+    c2.mg_setup(dev(U), -0.2, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(h["nv"], h["dims"], 172)),
+                MGParams(precision=h["prec"], n_init=0, n_setup=0))
+    x2, i2 = c2.mg_solve_shifted(sig, dev(b), 1e-10)
+    assert i2["converged"], i2
+    assert relmax(host(x3), host(x2)) < 1e-7
+    r = b - (h["op"].Q(host(x3)) - np.array(sig)[:, None, None] * host(x3))
+    for k in range(3):
+        assert np.linalg.norm(r[k]) <= 1.05e-10 * np.linalg.norm(b[k])
+
+
+def test_rqi_three_levels_lowest_eight_match_dense():
+    # tiny periodic workload with a third level (aggregates 2^4 of the 2^4
+    # lattice of aggregates: one level-2 site), 8 lowest pairs at 1e-10,
+    # each eigenvalue against the dense spectrum
+    from paper_1509_06865_amd import MGParams
+    from oracle.dirac import dense_Q
+    cfg = json.load(open(os.path.join(GOLDEN, "m0.json")))["tiny_periodic"]
+    dims, bc, m0 = tuple(cfg["dims"]), cfg["t_bc"], cfg["m0"]
+    print("[rqi 3 levels] 4^4 periodic, 8 lowest", flush=True)
+    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
+    c = _ctx(dims, bc)
+    c.mg_setup(dev(U), m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(8, dims, 102)),
+               MGParams(precision=1, coarse_m=40, coarse_tol=1e-8, coarse_restarts=8, n_setup=4, rqi_block=4,
+                        rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1, coarse2_m=64, coarse2_tol=1e-10),
+               agg2=(2, 2, 2, 2), nv2=4)
+    lam, V, res, info = c.rqi_lowmodes(8, 1e-10, V0=dev(lqsynth.gaussian_spinors(4, dims, 103)))
+    assert info["converged"], info
+    ev = np.linalg.eigvalsh(dense_Q(U, m0, Lattice(dims, bc)))
+    ref = np.array(sorted(ev[np.argsort(np.abs(ev))][:8], key=lambda x: (abs(x), x)))
+    lam = np.array(lam)
+    assert np.all(np.abs(lam - ref) <= 1e-10 * np.abs(ref)), (lam, ref)

@@ -56,12 +56,12 @@ def test_create_rejects_bad_arguments():
 
 
 def test_coarse_variant_switch_checks_its_argument():
-    # host-only: forcing a coarse-apply kernel accepts -1 (tuned) and 0..5
+    # host-only: forcing a coarse-apply kernel accepts -1 (tuned) and 0..6
     from paper_1509_06865_amd.lqmg import LQError, coarse_variant
-    for v in (-2, 6, 100):
+    for v in (-2, 7, 100):
         with pytest.raises(LQError):
             coarse_variant(v)
-    for v in range(6):
+    for v in range(7):
         coarse_variant(v)
     coarse_variant(-1)
 
