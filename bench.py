@@ -335,6 +335,88 @@ def kernel_only(args):
     log(f"kernel-only: copy of {a.numel() * 8} bytes x10")
 
 
+def learned_setup(args):
+    """Train the learned setup's network on generated 16^4 fields (eps between
+    0.2 and 0.4, bare mass m_c(eps) + 0.005 from tests/golden/mc_curve.json,
+    the 24 lowest eigenvectors of each field as targets), then compare it with
+    the plain adaptive setup on the 16^4 benchmark field (a field it was not
+    trained on): setup time, eigensolver sweeps and time, final residuals and
+    the projection loss of the test vectors each setup produces.  Prints one
+    JSON line."""
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import Context, MGParams
+    from paper_1509_06865_amd import learned as L
+    with open(os.path.join(ROOT, "tests", "golden", "mc_curve.json")) as f:
+        mc = json.load(f)
+    dims, agg, K = (16, 16, 16, 16), (4, 4, 4, 4), 24
+    V = int(np.prod(dims))
+    ctx = Context(dims, 1)
+    net = L.init_network(seed=5000)
+    phi_seed = 6000
+    losses, t_targets, t_train = [], 0.0, 0.0
+    n_fields = args.train_fields
+    for j in range(n_fields):
+        eps = 0.2 + 0.2 * j / max(n_fields - 1, 1)
+        m0 = float(np.interp(eps, mc["eps"], mc["m_c"])) + mc["target"]
+        U = torch.from_numpy(lqsynth.gauge_field(dims, eps, 1000 + j)).cuda()
+        phi0 = L.gaussian_fields(K, V, phi_seed + j)
+        a = time.time()
+        tgt, info = L.eigen_targets(ctx, U, m0, agg, phi0[:20].contiguous(), K, 1e-6)
+        torch.cuda.synchronize()
+        t_targets += time.time() - a
+        a = time.time()
+        for _ in range(args.train_steps):
+            losses.append(L.train_step(ctx, U, net, phi0, tgt, agg, args.train_lr))
+        torch.cuda.synchronize()
+        t_train += time.time() - a
+        log(f"field {j + 1}/{n_fields}: eps {eps:.3f} m0 {m0:.4f} targets converged {info['converged']} "
+            f"({info['sweeps']} sweeps), loss {losses[-args.train_steps]:.4f} -> {losses[-1]:.4f}")
+        del U, phi0, tgt
+    # evaluation on the benchmark field
+    gold = load_golden("medium")
+    m0 = gold["m0"]
+    U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
+    phi0 = L.gaussian_fields(K, V, gold["field_seed"] + 1)
+    ref_V, _ = L.eigen_targets(ctx, U, m0, agg, phi0[:20].contiguous(), K, 1e-6)
+    wl = WORKLOADS["medium"]
+    n_eig, guard, nv = wl["n_eig"], wl["guard"], 24
+    base = dict(wl["params"], precision=1, rqi_guard=guard, rayleigh_ritz=1, rqi_max_sweeps=args.max_sweeps)
+    plain = MGParams(**base)
+    learned = MGParams(**dict(base, n_setup=args.learned_n_setup, n_init=0))
+    V0 = device_gaussian(n_eig + guard - nv, dims, gold["field_seed"] + 2, torch)
+    out = {"train": {"fields": n_fields, "steps_per_field": args.train_steps, "lr": args.train_lr,
+                     "first_loss": losses[0], "last_loss": losses[-1],
+                     "mean_loss_first_10": float(np.mean(losses[:10])), "mean_loss_last_10": float(np.mean(losses[-10:])),
+                     "targets_s": round(t_targets, 1), "train_s": round(t_train, 1)}}
+    # the test vectors' projection loss against the 24 lowest modes
+    ctx.mg_setup(U, m0, agg, phi0[:nv].contiguous(), plain)
+    P_plain = ctx.get_interp()
+    X = L.propose(ctx, U, net, phi0)
+    out["loss_vs_lowest24"] = {"network_outputs": L.loss_of(ctx, X, ref_V, agg),
+                               "plain_setup_P": L.loss_of(ctx, P_plain, ref_V, agg),
+                               "random_start_vectors": L.loss_of(ctx, phi0, ref_V, agg)}
+    del P_plain
+    res = {}
+    for name in ("plain", "learned"):
+        if name == "plain":
+            lam, Vv, r, info, ts, tr = L.setup_and_solve(ctx, U, m0, agg, phi0[:nv].contiguous(), plain, n_eig,
+                                                         wl["tol"], V0)
+            info = dict(info, setup_s=ts, rqi_s=tr)
+        else:
+            lam, Vv, r, info = L.learned_solve(ctx, U, m0, agg, net, phi0, learned, plain, n_eig, wl["tol"], V0, nv)
+        res[name] = {"converged": info["converged"], "sweeps": info["sweeps"], "solves": info["solves"],
+                     "fgmres_iters": info["fgmres_iters"], "setup_s": round(info["setup_s"], 3),
+                     "rqi_s": round(info["rqi_s"], 3), "max_residual": float(max(r)),
+                     "learned_hierarchy_used": info.get("learned", False),
+                     "network_s": round(info.get("network_s", 0.0), 3)}
+        log(f"{name}: {res[name]}")
+        del Vv
+    out["solve"] = res
+    out["workload"] = f"16^4 eps={gold['eps']} m0={m0}, Nv={nv}, lowest {n_eig} at {wl['tol']}"
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +435,13 @@ def main():
     ap.add_argument("--nv2", type=int, default=None)
     ap.add_argument("--max-sweeps", type=int, default=40)
     ap.add_argument("--param", action="append", default=[], help="MGParams override name=value")
+    ap.add_argument("--learned", action="store_true",
+                    help="train the learned setup's network on generated 16^4 fields and compare it with the plain "
+                         "setup on the benchmark field")
+    ap.add_argument("--train-fields", type=int, default=200)
+    ap.add_argument("--train-steps", type=int, default=1)
+    ap.add_argument("--train-lr", type=float, default=1e-3)
+    ap.add_argument("--learned-n-setup", type=int, default=1)
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the roofline kernel class and a reference copy (for counter passes)")
     ap.add_argument("--coarse-variants", action="store_true",
@@ -366,6 +455,9 @@ def main():
         sys.exit(2)
     if args.coarse_variants:
         coarse_variants(args)
+        return
+    if args.learned:
+        learned_setup(args)
         return
     if args.kernel_only:
         kernel_only(args)
