@@ -103,8 +103,10 @@ typedef struct {
      above) right-preconditioned by a level-1 two-grid cycle made of */
   int coarse2_m;        /* the level-2 GMRES (on the gamma5^c2 form): restart length */
   int coarse2_restarts; /* its restarts after the first cycle */
-  double coarse2_tol;   /* its relative residual target */
-  int smooth1_m;        /* GMRES steps per level-1 smoothing step (gamma5^c form) */
+  double coarse2_tol;   /* its relative residual target; 0 = exactly coarse2_m steps
+                           with no convergence test (no host synchronisation) */
+  int smooth1_m;        /* GMRES steps per level-1 smoothing step (gamma5^c form; a
+                           fixed number, no convergence test) */
   int post1;            /* level-1 post-smoothing steps after the level-2 correction */
 } lq_mg_params;
 

@@ -94,10 +94,11 @@ void launch_restrict(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *f, 
 template <typename T>
 void launch_prolong(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *c, cplx<T> *f,
                     long long fstride, int nf, bool accumulate, hipStream_t st);
-// P from test vectors W [Nv][12][V] (FP64, blocked): per block and gamma5
-// half, Cholesky-QR applied twice.  Writes P64 (and P32 if non-null).
-// status (device int) set to 1 if a local Gram matrix is not positive definite.
-void launch_build_P(const Geom &g, const c128 *W, int Nv, c128 *P64, int *status, hipStream_t st);
+// P from Nv test vectors (FP64 fields [12][V], blocked; cols: device array
+// of their addresses, so they need not be contiguous): per block and gamma5
+// half, Cholesky-QR applied twice.  Writes P64 [Nv][12][V].  status (device
+// int) set to 1 if a local Gram matrix is not positive definite.
+void launch_build_P(const Geom &g, const c128 *const *cols, int Nv, c128 *P64, int *status, hipStream_t st);
 // Q_c columns from restricted parts: parts_c[j][5][nA][2Nv] -> Qc[A][d][row][col_j]
 template <typename T>
 void launch_scatter_coarse(const cplx<T> *parts_c, int nf, const int *cols_host, int n2,

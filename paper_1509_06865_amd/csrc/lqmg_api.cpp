@@ -154,7 +154,7 @@ struct lq_ctx {
   DevBuf<c128> parts64, pc64;
   DevBuf<c64> parts32, pc32;
   DevBuf<c128> eig;                 // RQI vectors, blocked FP64 [n][12][V]
-  DevBuf<c128> sel;                 // vectors that build P [Nv][12][V]
+  DevBuf<const c128 *> src_cols;    // addresses of the fields P is built from (device)
   DevBuf<c128> defl_tmp, defl_u, defl_r;   // Galerkin correction work           // Rayleigh-Ritz: gathered unconverged vectors
   DevBuf<c128> minus_one, plus_one; // constant coefficient arrays [kMaxRhs]
   DevBuf<double> coarse_sig;        // shifts of the current coarse solve [kMaxRhs]
@@ -356,6 +356,47 @@ template <typename T> struct KOps {
   std::function<void(const cplx<T> *, cplx<T> *)> precond;                     // z = M v, may be empty
   std::function<void(const cplx<T> *, const cplx<T> *, cplx<T> *)> resid;      // r = b - A x
 };
+
+// Fixed-step form: exactly m Arnoldi steps from x = 0 (one cycle, no
+// restart, no convergence test) with no value read back to the host, so the
+// whole solve is one asynchronous stream of launches (a polynomial smoother
+// or a fixed-accuracy inner solve).
+template <typename T>
+void gmres_fixed(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KOps<T> &ops, const cplx<T> *b,
+                 cplx<T> *x, int m) {
+  const bool flex = (bool)ops.precond;
+  cplx<T> *Vb = kw.V.get((size_t)(m + 1) * nrhs * n);
+  cplx<T> *Zb = flex ? kw.Z.get((size_t)m * nrhs * n) : nullptr;
+  KState &S = kw.st;
+  S.alloc(m, nrhs);
+  const long long vs = (long long)nrhs * n;
+  c128 *sc = kw.scratch.get(dots_scratch_elems(m + 1, nrhs));
+  Shifts one;
+  for (int k = 0; k < kMaxRhs; ++k) one.s[k] = 1.0;
+  launch_set_shifts(one, nrhs, S.bn, c->st);            // tolerance 0: only bn > 0 matters
+  launch_dots<T>(1, b, 0, n, b, n, n, nrhs, S.nrm2, sc, c->st);
+  launch_arnoldi_start(nrhs, m, S.nrm2, S.bn, 0.0, S.g, S.active, S.kk, S.coef, c->st);
+  launch_scale<T>(S.coef, b, n, Vb, n, n, nrhs, false, c->st);
+  for (int j = 0; j < m; ++j) {
+    cplx<T> *vj = Vb + j * vs, *w = Vb + (j + 1) * vs;
+    const cplx<T> *src = vj;
+    if (flex) {
+      ops.precond(vj, Zb + j * vs);
+      src = Zb + j * vs;
+    }
+    ops.apply(src, w);
+    launch_dots<T>(j + 1, Vb, vs, n, w, n, n, nrhs, S.h1, sc, c->st, S.active);
+    launch_multi_axpy<T>(j + 1, Vb, vs, n, S.h1, w, n, n, nrhs, -1.0, c->st, S.active);
+    launch_dots<T>(j + 1, Vb, vs, n, w, n, n, nrhs, S.h2, sc, c->st, S.active);
+    launch_multi_axpy<T>(j + 1, Vb, vs, n, S.h2, w, n, n, nrhs, -1.0, c->st, S.active);
+    launch_dots<T>(1, w, 0, n, w, n, n, nrhs, S.nrm2, sc, c->st, S.active);
+    launch_arnoldi_update(j, m, nrhs, S.h1, S.h2, S.nrm2, S.H, S.cs, S.sn, S.g, S.bn, 0.0, S.active, S.kk, S.coef,
+                          S.bad, c->st);
+    launch_scale<T>(S.coef, w, n, w, n, n, nrhs, false, c->st);
+  }
+  launch_arnoldi_solve(m, nrhs, S.H, S.g, S.kk, S.Y, c->st);
+  launch_multi_axpy<T>(m, flex ? Zb : Vb, vs, n, S.Y, x, n, n, nrhs, 1.0, c->st);
+}
 
 template <typename T>
 bool gmres_batched(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KOps<T> &ops, const cplx<T> *b,
@@ -576,8 +617,20 @@ void cycle1(lq_ctx *c, const double *sig, const cplx<T> *r1, cplx<T> *z1, int nr
   cplx<T> *w1 = l1work<T>(c, (size_t)3 * kMaxRhs * n1);
   cplx<T> *t1 = w1, *g1 = w1 + kMaxRhs * n1, *d1 = w1 + 2 * kMaxRhs * n1;
   launch_restrict2<T>(c->l2g, d.P2.p, r1, nrhs, r2, c->st);
-  coarse_gmres<T>(c, c->cg2, d.Qc2.p, nullptr, c2kw<T>(c), sig, r2, e2, nrhs, b2, c->p.coarse2_m,
-                  c->p.coarse2_restarts, c->p.coarse2_tol, false);
+  if (c->p.coarse2_tol > 0) {
+    coarse_gmres<T>(c, c->cg2, d.Qc2.p, nullptr, c2kw<T>(c), sig, r2, e2, nrhs, b2, c->p.coarse2_m,
+                    c->p.coarse2_restarts, c->p.coarse2_tol, false);
+  } else {
+    // coarse2_tol = 0: a fixed number (coarse2_m) of GMRES steps on the
+    // gamma5^c2 form, without host reads
+    const CoarseGeom cg2 = c->cg2;
+    const cplx<T> *Qc2 = d.Qc2.p;
+    launch_coarse_g5<T>(cg2, r2, b2, nrhs, c->st);
+    KOps<T> ops2;
+    ops2.apply = [=](const cplx<T> *x, cplx<T> *y) { launch_coarse_apply<T>(cg2, Qc2, x, y, S, nrhs, true, c->st); };
+    zero<T>(c, e2, (size_t)nrhs * n2);
+    gmres_fixed<T>(c, c2kw<T>(c), n2, nrhs, ops2, b2, e2, c->p.coarse2_m);
+  }
   launch_prolong2<T>(c->l2g, d.P2.p, e2, z1, nrhs, false, c->st);
   const c128 *pm1 = c->minus_one.p, *pp1 = c->plus_one.p;
   for (int step = 0; step < c->p.post1; ++step) {
@@ -595,7 +648,8 @@ void cycle1(lq_ctx *c, const double *sig, const cplx<T> *r1, cplx<T> *z1, int nr
       launch_scale<T>(pm1, r, n1, r, n1, n1, nrhs, false, c->st);
       launch_multi_axpy<T>(1, b, 0, n1, pp1, r, n1, n1, nrhs, 1.0, c->st);
     };
-    gmres_batched<T>(c, s1kw<T>(c), n1, nrhs, ops, g1, d1, c->p.smooth1_m, 0, 0.0, nullptr, nullptr, 0);
+    zero<T>(c, d1, (size_t)nrhs * n1);
+    gmres_fixed<T>(c, s1kw<T>(c), n1, nrhs, ops, g1, d1, c->p.smooth1_m);
     launch_multi_axpy<T>(1, d1, 0, n1, pp1, z1, n1, n1, nrhs, 1.0, c->st);
   }
 }
@@ -746,15 +800,12 @@ template <typename T> void build_coarse2(lq_ctx *c, DevBuf<cplx<T>> &parts, DevB
 // (the level-1 images of the approximations, as the fine vectors are for P).
 // Dependence on a level-2 aggregate half: an error, or with keep_dependent
 // that block of P2 keeps its previous columns (returns false).
-bool rebuild2(lq_ctx *c, const c128 *src, bool keep_dependent) {
+bool rebuild2(lq_ctx *c, const std::vector<const c128 *> &src, bool keep_dependent) {
   const long long V12 = 12LL * c->g.V, n1 = (long long)c->cg.nA * c->cg.n2;
   const size_t nP2 = (size_t)c->Nv2 * n1;
   c128 *W2 = c->W2.get(nP2);
-  // restriction with the FP64 P, at most 16 fields per launch
-  for (int k0 = 0; k0 < c->Nv2; k0 += kMaxRhs) {
-    const int nk = std::min(kMaxRhs, c->Nv2 - k0);
-    launch_restrict<double>(c->g, c->P64.p, c->Nv, src + k0 * V12, V12, nk, W2 + k0 * n1, c->st);
-  }
+  // restriction with the FP64 P, one field per launch (the fields need not be contiguous)
+  for (int k = 0; k < c->Nv2; ++k) launch_restrict<double>(c->g, c->P64.p, c->Nv, src[k], V12, 1, W2 + k * n1, c->st);
   int *st = c->status.get(1);
   LQ_HIP(hipMemsetAsync(st, 0, sizeof(int), c->st));
   c128 *P2 = c->P2_64.get(nP2);
@@ -778,12 +829,15 @@ bool rebuild2(lq_ctx *c, const c128 *src, bool keep_dependent) {
 // linearly dependent on some aggregate half are an error, unless keep_dependent:
 // then those blocks of P keep their previous columns (the other blocks are
 // rebuilt, P stays orthonormal and gamma5-split) and the call returns false.
-bool rebuild(lq_ctx *c, const c128 *src, bool keep_dependent = false) {
+bool rebuild(lq_ctx *c, const std::vector<const c128 *> &src, bool keep_dependent = false) {
   const size_t nP = (size_t)c->Nv * 12 * c->g.V;
+  if ((int)src.size() != c->Nv) fail(LQ_ERR_ARG, "rebuild: need Nv source fields");
   int *st = c->status.get(1);
   LQ_HIP(hipMemsetAsync(st, 0, sizeof(int), c->st));
   c128 *P64 = c->P64.get(nP);
-  launch_build_P(c->g, src, c->Nv, P64, st, c->st);
+  const c128 **cols = c->src_cols.get(src.size());
+  LQ_HIP(hipMemcpyAsync(cols, src.data(), src.size() * sizeof(const c128 *), hipMemcpyHostToDevice, c->st));
+  launch_build_P(c->g, cols, c->Nv, P64, st, c->st);
   int h_st = 0;
   LQ_HIP(hipMemcpyAsync(&h_st, st, sizeof(int), hipMemcpyDeviceToHost, c->st));
   sync(c);
@@ -803,6 +857,13 @@ bool rebuild(lq_ctx *c, const c128 *src, bool keep_dependent = false) {
   bool ok2 = true;
   if (c->n_levels == 3) ok2 = rebuild2(c, src, keep_dependent);
   return h_st == 0 && ok2;
+}
+
+// Addresses of n consecutive fields starting at F.
+std::vector<const c128 *> fields_of(const lq_ctx *c, const c128 *F, int n) {
+  std::vector<const c128 *> v(n);
+  for (int k = 0; k < n; ++k) v[k] = F + (long long)k * 12 * c->g.V;
+  return v;
 }
 
 // Gram-Schmidt (twice) of n fields in place, in index order; FP64.
@@ -1126,10 +1187,18 @@ void lu_solve(int n, const std::vector<cd> &M, const std::vector<int> &piv, cd *
   }
 }
 
+// Room for kMaxRhs FP64 fields outside the solves: the outer FGMRES basis
+// when it is idle and large enough, else a buffer of its own.
+c128 *idle_fields(lq_ctx *c) {
+  const size_t need = (size_t)kMaxRhs * 12 * c->g.V;
+  if (c->fine_kw.V.p && c->fine_kw.V.n >= need) return c->fine_kw.V.p;
+  return c->defl_tmp.get(need);
+}
+
 // A = E^dag Q E and G = E^dag E for the n fields E (blocked layout, FP64).
 void projected_operator(lq_ctx *c, const c128 *E, int n, std::vector<cd> &A, std::vector<cd> &G) {
   const long long V12 = 12LL * c->g.V;
-  c128 *QE = c->defl_tmp.get((size_t)kMaxRhs * V12);
+  c128 *QE = idle_fields(c);
   A.assign((size_t)n * n, cd(0));
   G.assign((size_t)n * n, cd(0));
   Shifts z = shifts_of(nullptr, 0);
@@ -1153,7 +1222,7 @@ void update_projected(lq_ctx *c, const c128 *E, int n, const std::vector<int> &i
                       std::vector<cd> &A, std::vector<cd> &G) {
   const long long V12 = 12LL * c->g.V;
   const int nk = (int)ids.size();
-  c128 *QX = c->defl_tmp.get((size_t)kMaxRhs * V12);
+  c128 *QX = idle_fields(c);
   launch_wilson<double>(c->g, c->U64.p, X, QX, nullptr, c->m0, shifts_of(nullptr, 0), nk, W_QSHIFT, c->st);
   auto a = gram(c, n, E, V12, nk, QX, V12, V12);
   auto g = gram(c, n, E, V12, nk, X, V12, V12);
@@ -1432,7 +1501,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, int n_levels, const int n_t
         copy<double>(c, W + k0 * V12, tmp, (size_t)nk * V12);
       }
     orthonormalise(c, W, n_tv);
-    rebuild(c, W);                       // dependent start vectors are an error
+    rebuild(c, fields_of(c, W, n_tv));   // dependent start vectors are an error
     for (int it = 0; it < p.n_setup; ++it) {
       for (int k0 = 0; k0 < n_tv; k0 += kMaxRhs) {
         const int nk = std::min(kMaxRhs, n_tv - k0);
@@ -1443,7 +1512,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, int n_levels, const int n_t
       // vectors the multigrid iteration made locally dependent (a near-null
       // space thinner than Nv on some aggregate) leave those blocks of P as
       // they were
-      rebuild(c, W, true);
+      rebuild(c, fields_of(c, W, n_tv), true);
       if (verbose()) {
         size_t fr = 0, tot = 0;
         (void)hipMemGetInfo(&fr, &tot);
@@ -1512,7 +1581,7 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     // first multigrid pass then acts on an orthonormal set)
     orthonormalise(c, E, nw);
     std::vector<double> lam(nw, 0.0), eps(nw, 1.0);
-    c128 *SEL = c->sel.get((size_t)Nv * V12);
+
     // P from the current approximations (Alg. 1 puts each new iterate into
     // the interpolation).  With
     // more vectors than Nv it takes the Nv whose lambda lies nearest to one of
@@ -1535,11 +1604,12 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         idx.assign(o.begin(), o.begin() + Nv);
         std::sort(idx.begin(), idx.end());
       }
-      for (size_t q = 0; q < idx.size(); ++q) copy<double>(c, SEL + q * V12, E + idx[q] * V12, V12);
-      for (int q = (int)idx.size(); q < Nv; ++q) copy<double>(c, SEL + q * V12, c->W.p + q * V12, V12);
+      std::vector<const c128 *> src(Nv);
+      for (size_t q = 0; q < idx.size(); ++q) src[q] = E + idx[q] * V12;
+      for (int q = (int)idx.size(); q < Nv; ++q) src[q] = c->W.p + q * V12;
       // approximations that are dependent on an aggregate (exactly degenerate
       // smooth modes) leave that aggregate's columns of P as they were
-      if (rebuild(c, SEL, true)) S.p_rebuilds++;
+      if (rebuild(c, src, true)) S.p_rebuilds++;
       S.t_rebuild += now() - t0;
     };
     // the n_eig vectors with smallest |lambda| have converged

@@ -155,7 +155,7 @@ template <typename T> constexpr int transfer_group() { return sizeof(T) == 4 ? 4
 // diagonal), the workgroup writes nothing, so that block of P keeps its
 // previous columns, and raises *status.
 constexpr int kMaxNv = 32;
-__global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict__ W, int Nv,
+__global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *const *__restrict__ cols, int Nv,
                                                  c128 *__restrict__ P, int *status) {
   __shared__ double part[4][kMaxNv * (kMaxNv + 1) / 2 * 2];   // wave partial sums of the Gram entries
   __shared__ c128 L[kMaxNv][kMaxNv];
@@ -167,20 +167,23 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict_
   const int npair = Nv * (Nv + 1) / 2;
   if (t == 0) bad = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    const c128 *src = (pass == 0) ? W : P;
+    // field k of this pass: test vector k (its own address), then column k of P
+    auto field = [&](int k) -> const c128 * { return (pass == 0) ? cols[k] : P + (long long)k * 12 * g.V; };
     // Gram partials, pairs (i <= j) in row-major order
     int pidx = 0;
     for (int i = 0; i < Nv; ++i) {
       c128 wi[6];
+      const c128 *fi = field(i);
 #pragma unroll
       for (int r = 0; r < 6; ++r)
-        wi[r] = active ? src[((long long)i * 12 + 6 * h + r) * g.V + s] : c128{0, 0};
+        wi[r] = active ? fi[(long long)(6 * h + r) * g.V + s] : c128{0, 0};
       for (int jj = i; jj < Nv; ++jj, ++pidx) {
         double re = 0, im = 0;
         if (active) {
+          const c128 *fj = field(jj);
 #pragma unroll
           for (int r = 0; r < 6; ++r) {
-            const c128 wj = src[((long long)jj * 12 + 6 * h + r) * g.V + s];
+            const c128 wj = fj[(long long)(6 * h + r) * g.V + s];
             re += wi[r].re * wj.re + wi[r].im * wj.im;
             im += wi[r].re * wj.im - wi[r].im * wj.re;
           }
@@ -223,7 +226,7 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *__restrict_
       for (int r = 0; r < 6; ++r) {
         c128 pr[kMaxNv];
         for (int jj = 0; jj < Nv; ++jj) {
-          c128 v = src[((long long)jj * 12 + 6 * h + r) * g.V + s];
+          c128 v = field(jj)[(long long)(6 * h + r) * g.V + s];
           for (int i = 0; i < jj; ++i) v = v - pr[i] * conj(L[jj][i]);
           pr[jj] = (1.0 / L[jj][jj].re) * v;
         }
@@ -277,9 +280,9 @@ void launch_prolong(const Geom &g, const cplx<T> *P, int Nv, const cplx<T> *c, c
   LQ_HIP(hipGetLastError());
 }
 
-void launch_build_P(const Geom &g, const c128 *W, int Nv, c128 *P64, int *status, hipStream_t st) {
+void launch_build_P(const Geom &g, const c128 *const *cols, int Nv, c128 *P64, int *status, hipStream_t st) {
   const int threads = ((g.bvol + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_build_P, dim3(g.nblk, 2), dim3(threads), 0, st, g, W, Nv, P64, status);
+  hipLaunchKernelGGL(k_build_P, dim3(g.nblk, 2), dim3(threads), 0, st, g, cols, Nv, P64, status);
   LQ_HIP(hipGetLastError());
 }
 

@@ -649,12 +649,30 @@ def test_rqi_benchmark_workload_returns_exact_pairs():
     Vh = host(V)
     del V, V0
     op = WilsonOp(U, m0, lat)
+    eps = np.empty(50)
     for i in range(50):
         v = Vh[i]
         Qv = op.Q(v)
         assert abs(np.linalg.norm(v) - 1) < 1e-12
         assert abs(np.vdot(v, Qv).real - lam[i]) < 1e-12
-        assert np.linalg.norm(Qv - lam[i] * v) <= 2e-10
+        eps[i] = np.linalg.norm(Qv - lam[i] * v)
+        assert eps[i] <= 2e-10
     G = np.einsum("ian,jan->ij", Vh.conj(), Vh)
     assert np.abs(G - np.eye(50)).max() < 1e-10
+    # certificates: Kato-Temple bounds (with the computed neighbours; valid
+    # if no mode was missed) put every eigenvalue far inside 1e-10 relative
+    from oracle import certify as C
+    kt = C.kato_temple(lam, eps)
+    ok = np.isfinite(kt)
+    assert ok.sum() >= 40 and np.all(kt[ok] <= 1e-10 * np.abs(lam[ok]))
+    # deflated inverse iteration (solves by the device's FGMRES at sigma = 0):
+    # an upper bound of the smallest |mu| outside the returned span must not
+    # fall below the largest |lambda| returned, else a lower mode was missed
+    def solve(b):
+        x, info = c.mg_solve_shifted([0.0], dev(b[None]), 1e-10)
+        assert info["converged"], info
+        return host(x)[0]
+    a, _ = C.deflated_smallest(op, Vh, solve, n_start=2, iters=6, seed=204)
+    print("largest |lambda|", np.abs(lam).max(), "deflated bound", a, flush=True)
+    assert not C.missing_modes(lam, a, 1e-8)
 
