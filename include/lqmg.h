@@ -220,6 +220,37 @@ int lq_inner_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c1
 int lq_inner_products_noalloc(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W,
                               long long n, lq_c128 *out);
 
+/* ---- approximate low-mode averaging (sec. 3.2, 3.3) ------------------------- */
+/* Low-mode parts from n approximate eigenpairs (lambda[i], V[i], eps[i]) of Q
+ * (V: device [n][12][V] canonical, orthonormal; lambda, eps: host double[n]).
+ * The pairs with eps_i <= cutoff |lambda_i| are kept (sec. 3.3); with A the
+ * projected matrix <v_i|Q|v_j> of the kept ones, the low-mode inverse is
+ * sum_ij (A^-1)_ij |v_i><v_j| (sec. 3.2).  Outputs per timeslice t (t slowest
+ * in the site index; host double[2*T], re/im interleaved; either may be NULL):
+ *   loop_low[t] = sum over the sites x of timeslice t of tr (Q~_low^-1)_{x,x};
+ *   conn_low[t] = (1/V) sum over x, y with t_x - t_y = t (mod T) of
+ *                 tr[(Q~_low^-1)_{x,y} (Q~_low^-1)_{y,x}];
+ * n_kept (nullable): the number of pairs kept (at most 192).  Needs no
+ * hierarchy.  Errors: LQ_ERR_ARG, LQ_ERR_NUMERIC (A singular). */
+int lma_low(lq_ctx *ctx, const lq_c128 *U, double m0, int n, const lq_c128 *V, const double *lambda,
+            const double *eps, double cutoff, double *loop_low, double *conn_low, int *n_kept);
+/* High-mode part of the loop, one sample per noise field eta (device
+ * [n_noise][12][V] canonical, e.g. Z2 + i Z2 noise): s = Q^-1 R~ eta with the
+ * oblique projector R~ = 1 - Q V A^-1 V^dag of the kept pairs (sec. 3.2; all
+ * pairs dropped or n = 0: R~ = 1), solved to the relative residual tol by
+ * FGMRES with the context's multigrid (sigma = 0); loop_high[k][t] = sum over
+ * timeslice t of eta_k^dag s_k (host double[n_noise][2*T], re/im).  The mean
+ * over the noise of loop_high plus loop_low estimates the loop without bias
+ * (Q~_low^-1 + Q^-1 R~ = Q^-1 for any approximations).  Needs mg_setup.
+ * Errors: LQ_ERR_STATE, LQ_ERR_ARG, LQ_ERR_NUMERIC (a solve did not converge). */
+int lma_high(lq_ctx *ctx, const lq_c128 *U, double m0, int n, const lq_c128 *V, const double *lambda,
+             const double *eps, double cutoff, int n_noise, const lq_c128 *eta, double tol, double *loop_high);
+/* out[t][i][k] = sum over timeslice t (and the 12 components) of conj(E_i) W_k
+ * for canonical fields E [nb][12][V], W [nw][12][V] (device); out host
+ * [T][nb][nw] c128; 1 <= nw <= 16.  The per-timeslice overlaps of sec. 3.2's
+ * estimators.  Errors: LQ_ERR_ARG. */
+int lq_timeslice_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W, lq_c128 *out);
+
 /* ---- learned setup: network layer (not part of the paper) ------------------- */
 /* One parallel-transport convolution of the network that proposes multigrid
  * test vectors:  out[o](x) = sum_{i < c_in} sum_{d in {-1,0,1}^4}

@@ -231,3 +231,62 @@ void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128
 }
 
 }  // namespace lq
+
+namespace lq {
+namespace {
+
+// out[t][i][k] = sum over the sites of timeslice t and the 12 components of
+// conj(E_i) W_k, for canonical-layout fields [12][V] (t slowest, L3 sites per
+// timeslice).  One workgroup per (t, i): its threads stride over the
+// timeslice's 12 L3 entries with nw partial sums each, then a fixed-order
+// reduction (wave shuffles, then the waves in order).
+constexpr int kSliceMaxW = 16;
+__global__ void __launch_bounds__(256) k_slice_products(int nb, const c128 *__restrict__ E, int nw,
+                                                        const c128 *__restrict__ W, long long V, long long L3,
+                                                        c128 *__restrict__ out) {
+  __shared__ double red[4][kSliceMaxW][2];
+  const int t = blockIdx.x, i = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double sr[kSliceMaxW], si[kSliceMaxW];
+#pragma unroll
+  for (int k = 0; k < kSliceMaxW; ++k) { sr[k] = 0; si[k] = 0; }
+  const c128 *Ei = E + (long long)i * 12 * V;
+  for (long long e = threadIdx.x; e < 12 * L3; e += blockDim.x) {
+    const long long c = e / L3, x = t * L3 + (e - c * L3);
+    const c128 a = Ei[c * V + x];
+#pragma unroll
+    for (int k = 0; k < kSliceMaxW; ++k) {
+      if (k >= nw) break;
+      const c128 b = W[(long long)k * 12 * V + c * V + x];
+      sr[k] += a.re * b.re + a.im * b.im;
+      si[k] += a.re * b.im - a.im * b.re;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kSliceMaxW; ++k) {
+    for (int off = 32; off > 0; off >>= 1) {
+      sr[k] += __shfl_xor(sr[k], off, 64);
+      si[k] += __shfl_xor(si[k], off, 64);
+    }
+    if (lane == 0) { red[wave][k][0] = sr[k]; red[wave][k][1] = si[k]; }
+  }
+  __syncthreads();
+  if (threadIdx.x < nw) {
+    const int k = threadIdx.x;
+    double a = 0, b = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += red[w][k][0]; b += red[w][k][1]; }
+    out[((long long)t * nb + i) * nw + k] = c128{a, b};
+  }
+}
+
+}  // namespace
+
+void launch_slice_products(int nb, const c128 *E, int nw, const c128 *W, long long V, int T, c128 *out,
+                           hipStream_t st) {
+  if (nb < 1 || nw < 1 || nw > kSliceMaxW || T < 1 || V % T)
+    throw HipError(hipErrorInvalidValue, "launch_slice_products: nw <= 16, T divides V", __FILE__, __LINE__);
+  hipLaunchKernelGGL(k_slice_products, dim3(T, nb), dim3(256), 0, st, nb, E, nw, W, V, V / T, out);
+  LQ_HIP(hipGetLastError());
+}
+
+}  // namespace lq

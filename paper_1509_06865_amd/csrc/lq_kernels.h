@@ -56,6 +56,10 @@ void launch_gram(int nb, const c128 *E, long long estride, int nw, const c128 *W
 size_t gram_scratch_elems(long long n);
 // complex partial sums one element chunk of the Gram kernel leaves for nb basis vectors
 inline size_t gram_chunk_elems(int nb) { return (size_t)nb * 16; }
+// out[t][i][k] = sum over timeslice t (canonical layout, t slowest) of <E_i, W_k>
+// summed over the 12 components; nw <= 16, out device [T][nb][nw].
+void launch_slice_products(int nb, const c128 *E, int nw, const c128 *W, long long V, int T, c128 *out,
+                           hipStream_t st);
 // U_k (+)= sum_i Y[i][k] E_i for k < nw; Y device [nb][nw].
 void launch_combine(int nb, const c128 *E, long long estride, int nw, const c128 *Y, c128 *U, long long ustride,
                     long long n, bool accumulate, hipStream_t st);

@@ -173,6 +173,8 @@ struct lq_ctx {
   DevBuf<c64> l1w32, l2w32;          // (FP32)
   DevBuf<c128> parts2_64, pc2_64;
   DevBuf<c64> parts2_32, pc2_32;
+  DevBuf<c128> lma_V, lma_W, lma_X;  // approximate low-mode averaging: kept vectors, work fields
+  DevBuf<c128> lma_out;
   int coarse_iters = 0;
   // captured coarse-GMRES chunks, keyed by shape, step range and every pointer
   // they use; cap_st is the private stream they are captured on
@@ -1997,6 +1999,176 @@ int lq_inner_products_noalloc(lq_ctx *c, int nb, const lq_c128 *E, int nw, const
         (long long)((kNoAllocBytes - kNoAllocOutBytes) / (gram_chunk_elems(nb) * sizeof(c128)));
     launch_gram(nb, (const c128 *)E, n, nw, (const c128 *)W, n, n, dout, part, c->st, max_chunks);
     LQ_HIP(hipMemcpyAsync(out, dout, (size_t)nb * nw * sizeof(c128), hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    return LQ_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Approximate low-mode averaging (sec. 3.2-3.3): the kept approximations
+// (eps_i <= cutoff |lambda_i|) copied to lma_V, and A = V^dag Q V with its LU.
+struct LmaLow {
+  int n = 0;
+  std::vector<cd> A, LU;
+  std::vector<int> piv;
+};
+
+LmaLow lma_prepare(lq_ctx *c, const c128 *U, double m0, int n, const c128 *V, const double *lam, const double *eps,
+                   double cutoff) {
+  const long long V12 = 12LL * c->gcan.V;
+  std::vector<int> keep;
+  for (int i = 0; i < n; ++i)
+    if (eps[i] <= cutoff * std::fabs(lam[i])) keep.push_back(i);
+  LmaLow L;
+  L.n = (int)keep.size();
+  if (L.n == 0) return L;
+  if (L.n > 192) fail(LQ_ERR_ARG, "at most 192 approximations are kept");
+  c128 *Vk = c->lma_V.get((size_t)L.n * V12);
+  for (int q = 0; q < L.n; ++q) copy<double>(c, Vk + q * V12, V + keep[q] * V12, V12);
+  c128 *QV = c->lma_W.get((size_t)kMaxRhs * V12);
+  L.A.assign((size_t)L.n * L.n, cd(0));
+  Shifts z = shifts_of(nullptr, 0);
+  for (int j0 = 0; j0 < L.n; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, L.n - j0);
+    launch_wilson<double>(c->gcan, U, Vk + j0 * V12, QV, nullptr, m0, z, nk, W_QSHIFT, c->st);
+    auto a = gram(c, L.n, Vk, V12, nk, QV, V12, V12);
+    for (int i = 0; i < L.n; ++i)
+      for (int k = 0; k < nk; ++k) L.A[(size_t)i * L.n + j0 + k] = a[(size_t)i * nk + k];
+  }
+  L.LU = L.A;
+  if (!lu_factor(L.n, L.LU, L.piv)) fail(LQ_ERR_NUMERIC, "the projected matrix A is singular");
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lma_low(lq_ctx *c, const lq_c128 *U, double m0, int n, const lq_c128 *V, const double *lam, const double *eps,
+            double cutoff, double *loop_low, double *conn_low, int *n_kept) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !V || !lam || !eps || n < 1 || !(cutoff > 0)) fail(LQ_ERR_ARG, "lma_low: bad arguments");
+    const int T = c->L[3];
+    const long long Vol = c->gcan.V, V12 = 12LL * Vol;
+    LmaLow L = lma_prepare(c, (const c128 *)U, m0, n, (const c128 *)V, lam, eps, cutoff);
+    if (n_kept) *n_kept = L.n;
+    std::vector<double> lr(2 * T, 0.0), cr(2 * T, 0.0);
+    if (L.n > 0) {
+      const int nn = L.n;
+      // O[t][j][i] = sum over timeslice t of <v_j, v_i>
+      std::vector<cd> O((size_t)T * nn * nn);
+      c128 *dout = c->lma_out.get((size_t)T * nn * kMaxRhs);
+      for (int k0 = 0; k0 < nn; k0 += kMaxRhs) {
+        const int nk = std::min(kMaxRhs, nn - k0);
+        launch_slice_products(nn, c->lma_V.p, nk, c->lma_V.p + k0 * V12, Vol, T, dout, c->st);
+        std::vector<cd> h((size_t)T * nn * nk);
+        LQ_HIP(hipMemcpyAsync(h.data(), dout, h.size() * sizeof(cd), hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        for (int t = 0; t < T; ++t)
+          for (int j = 0; j < nn; ++j)
+            for (int k = 0; k < nk; ++k) O[((size_t)t * nn + j) * nn + k0 + k] = h[((size_t)t * nn + j) * nk + k];
+      }
+      // M(t) = A^{-1} O(t) (column by column through the LU factors)
+      std::vector<cd> M((size_t)T * nn * nn), col(nn);
+      for (int t = 0; t < T; ++t)
+        for (int i = 0; i < nn; ++i) {
+          for (int j = 0; j < nn; ++j) col[j] = O[((size_t)t * nn + j) * nn + i];
+          lu_solve(nn, L.LU, L.piv, col.data());
+          for (int j = 0; j < nn; ++j) M[((size_t)t * nn + j) * nn + i] = col[j];
+        }
+      // L_low(t) = tr M(t);  C_low(t) = (1/Vol) sum_t0 tr[M(t0) M(t0 + t)]
+      for (int t = 0; t < T; ++t) {
+        cd tr = 0;
+        for (int i = 0; i < nn; ++i) tr += M[((size_t)t * nn + i) * nn + i];
+        lr[2 * t] = tr.real();
+        lr[2 * t + 1] = tr.imag();
+      }
+      for (int t = 0; t < T; ++t) {
+        cd acc = 0;
+        for (int t0 = 0; t0 < T; ++t0) {
+          const cd *Ma = &M[(size_t)t0 * nn * nn], *Mb = &M[(size_t)((t0 + t) % T) * nn * nn];
+          for (int i = 0; i < nn; ++i)
+            for (int j = 0; j < nn; ++j) acc += Ma[(size_t)i * nn + j] * Mb[(size_t)j * nn + i];
+        }
+        acc /= (double)Vol;
+        cr[2 * t] = acc.real();
+        cr[2 * t + 1] = acc.imag();
+      }
+    }
+    if (loop_low) std::memcpy(loop_low, lr.data(), lr.size() * sizeof(double));
+    if (conn_low) std::memcpy(conn_low, cr.data(), cr.size() * sizeof(double));
+    return LQ_OK;
+  });
+}
+
+int lma_high(lq_ctx *c, const lq_c128 *U, double m0, int n, const lq_c128 *V, const double *lam, const double *eps,
+             double cutoff, int n_noise, const lq_c128 *eta, double tol, double *loop_high) {
+  return guard(c, [&] {
+    need_mg(c);
+    if (!U || !eta || !loop_high || n_noise < 1 || n < 0 || (n > 0 && (!V || !lam || !eps)) || !(tol > 0) ||
+        !(cutoff > 0))
+      fail(LQ_ERR_ARG, "lma_high: bad arguments");
+    const int T = c->L[3];
+    const long long Vol = c->gcan.V, V12 = 12LL * Vol;
+    LmaLow L;
+    if (n > 0) L = lma_prepare(c, (const c128 *)U, m0, n, (const c128 *)V, lam, eps, cutoff);
+    c128 *R = c->lma_W.get((size_t)kMaxRhs * V12);     // R~ eta, then the solution
+    c128 *X = c->lma_X.get((size_t)kMaxRhs * V12);
+    c128 *b = c->tmpA.get((size_t)kMaxRhs * V12), *xb = c->tmpB.get((size_t)kMaxRhs * V12);
+    c128 *dout = c->lma_out.get((size_t)T * kMaxRhs);
+    std::vector<double> zs(kMaxRhs, 0.0);
+    for (int k0 = 0; k0 < n_noise; k0 += kMaxRhs) {
+      const int nk = std::min(kMaxRhs, n_noise - k0);
+      const c128 *E = (const c128 *)eta + k0 * V12;
+      copy<double>(c, R, E, (size_t)nk * V12);
+      if (L.n > 0) {
+        // R~ eta = eta - Q V A^{-1} V^dag eta
+        auto cv = gram(c, L.n, c->lma_V.p, V12, nk, E, V12, V12);     // [n][nk]
+        std::vector<cd> Y(cv.size()), col(L.n);
+        for (int k = 0; k < nk; ++k) {
+          for (int i = 0; i < L.n; ++i) col[i] = cv[(size_t)i * nk + k];
+          lu_solve(L.n, L.LU, L.piv, col.data());
+          for (int i = 0; i < L.n; ++i) Y[(size_t)i * nk + k] = col[i];
+        }
+        combine(c, L.n, c->lma_V.p, V12, nk, Y, 1.0, X, V12, V12, false);                 // X = V y
+        launch_wilson<double>(c->gcan, (const c128 *)U, X, xb, R, m0, shifts_of(nullptr, 0), nk, W_RESID, c->st);
+        copy<double>(c, R, xb, (size_t)nk * V12);                                        // R = eta - Q V y
+      }
+      // s = Q^{-1} R~ eta by the multigrid-preconditioned FGMRES (sigma = 0)
+      launch_permute<double>(c->g, R, b, nk, true, c->st);
+      int its[kMaxRhs];
+      double rr[kMaxRhs];
+      const bool ok = solve_shifted(c, nk, zs.data(), b, xb, tol, its, rr, c->p.fgmres_restarts);
+      if (!ok) fail(LQ_ERR_NUMERIC, "lma_high: a deflated solve did not reach the tolerance");
+      launch_permute<double>(c->g, xb, X, nk, false, c->st);
+      // per timeslice: sum over t of eta_k^dag s_k
+      for (int k = 0; k < nk; ++k) {
+        launch_slice_products(1, E + k * V12, 1, X + k * V12, Vol, T, dout, c->st);
+        std::vector<cd> h(T);
+        LQ_HIP(hipMemcpyAsync(h.data(), dout, T * sizeof(cd), hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        for (int t = 0; t < T; ++t) {
+          loop_high[((size_t)(k0 + k) * T + t) * 2] = h[t].real();
+          loop_high[((size_t)(k0 + k) * T + t) * 2 + 1] = h[t].imag();
+        }
+      }
+    }
+    return LQ_OK;
+  });
+}
+
+int lq_timeslice_products(lq_ctx *c, int nb, const lq_c128 *E, int nw, const lq_c128 *W, lq_c128 *out) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (nb < 1 || nw < 1 || nw > kMaxRhs || !E || !W || !out) fail(LQ_ERR_ARG, "lq_timeslice_products: bad arguments");
+    const int T = c->L[3];
+    c128 *dout = c->lma_out.get((size_t)T * nb * nw);
+    launch_slice_products(nb, (const c128 *)E, nw, (const c128 *)W, c->gcan.V, T, dout, c->st);
+    LQ_HIP(hipMemcpyAsync(out, dout, (size_t)T * nb * nw * sizeof(c128), hipMemcpyDeviceToHost, c->st));
     sync(c);
     return LQ_OK;
   });

@@ -25,7 +25,7 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
             "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc", "mg_info2",
-            "mg_get_level2"]
+            "mg_get_level2", "lma_low", "lma_high", "lq_timeslice_products"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -124,6 +124,9 @@ def load():
         "q_apply_c64": (i, [vp, vp, d, vp, vp, i]),
         "mg_setup": (i, [vp, vp, d, i, ip, ip, vp, C.POINTER(_Params)]),
         "mg_info2": (i, [vp, ip, ip]),
+        "lma_low": (i, [vp, vp, d, i, vp, dp, dp, d, dp, dp, ip]),
+        "lma_high": (i, [vp, vp, d, i, vp, dp, dp, d, i, vp, d, dp]),
+        "lq_timeslice_products": (i, [vp, i, vp, i, vp, vp]),
         "mg_get_level2": (i, [vp, vp, vp]),
         "mg_solve_shifted": (i, [vp, i, dp, vp, vp, d, C.POINTER(_SolveStats)]),
         "rqi_lowmodes": (i, [vp, i, d, dp, vp, dp, vp, i, C.POINTER(_RQIStats)]),
@@ -450,6 +453,44 @@ class Context:
         out = np.empty((nb, nw), dtype=np.complex128)
         self._check(self.lib.lq_inner_products_noalloc(self.h, nb, _ptr(E), nw, _ptr(W), n,
                                                        C.c_void_p(out.ctypes.data)))
+        return out
+
+    # -- approximate low-mode averaging (sec. 3.2, 3.3) ---------------------------
+    def lma_low(self, U, m0, V, lam, eps, cutoff):
+        """Low-mode loop and connected correlator per timeslice from approximate
+        eigenpairs (V device [n, 12, V] complex128): (loop_low [T], conn_low [T], n_kept)."""
+        import numpy as np
+        n, T = int(V.shape[0]), self.dims[3]
+        _need(V, "V", (n, 12, self.V), torch.complex128)
+        lo = np.zeros(2 * T)
+        co = np.zeros(2 * T)
+        kept = C.c_int()
+        self._check(self.lib.lma_low(self.h, _ptr(U), float(m0), n, _ptr(V), _dbl(lam), _dbl(eps), float(cutoff),
+                                     lo.ctypes.data_as(C.POINTER(C.c_double)),
+                                     co.ctypes.data_as(C.POINTER(C.c_double)), C.byref(kept)))
+        return lo[0::2] + 1j * lo[1::2], co[0::2] + 1j * co[1::2], kept.value
+
+    def lma_high(self, U, m0, V, lam, eps, cutoff, eta, tol=1e-10):
+        """High-mode loop samples [n_noise, T] for noise fields eta (device [n_noise, 12, V])."""
+        import numpy as np
+        T = self.dims[3]
+        n = 0 if V is None else int(V.shape[0])
+        if n:
+            _need(V, "V", (n, 12, self.V), torch.complex128)
+        _need(eta, "eta", (int(eta.shape[0]), 12, self.V), torch.complex128)
+        out = np.zeros((int(eta.shape[0]), 2 * T))
+        self._check(self.lib.lma_high(self.h, _ptr(U), float(m0), n, _ptr(V) if n else None,
+                                      _dbl(lam) if n else None, _dbl(eps) if n else None, float(cutoff),
+                                      int(eta.shape[0]), _ptr(eta), float(tol),
+                                      out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out[:, 0::2] + 1j * out[:, 1::2]
+
+    def timeslice_products(self, E, W):
+        """[T, nb, nw] per-timeslice inner products <E_i, W_k> (device complex128 fields)."""
+        import numpy as np
+        nb, nw, T = int(E.shape[0]), int(W.shape[0]), self.dims[3]
+        out = np.empty((T, nb, nw), dtype=np.complex128)
+        self._check(self.lib.lq_timeslice_products(self.h, nb, _ptr(E), nw, _ptr(W), C.c_void_p(out.ctypes.data)))
         return out
 
     def cycle(self, sigma, r):
