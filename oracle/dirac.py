@@ -12,8 +12,9 @@ Conventions
                        + (1 + gamma_mu) U_mu(n - mu)^dag psi(n - mu) ],
     Wilson parameter r = 1; a hop in t across the boundary t = T-1 <-> 0 is
     multiplied by ``t_bc`` (-1 antiperiodic, +1 periodic).  The paper names the
-    (clover-improved) Wilson operator without writing it; the clover term is
-    not part of this workload (c_sw = 0).
+    (clover-improved) Wilson operator without writing it; the benchmark
+    workloads take c_sw = 0, and WilsonOp adds the clover term of clover.py
+    for c_sw != 0.
   * fields are [..., 12, V] with component 3*s + c and canonical site order
     (x fastest); links are U[mu, 3*a + b, V].
 """
@@ -206,9 +207,14 @@ class WilsonOp:
     Vectors are flattened as index (3s + c) * V + n.  ``scipy.sparse`` only
     performs the matrix-vector products."""
 
-    def __init__(self, U, m0: float, lat: Lattice):
+    def __init__(self, U, m0: float, lat: Lattice, csw: float = 0.0):
         import scipy.sparse as sp
         self.U, self.m0, self.lat = U, float(m0), lat
+        self.csw = float(csw)
+        self.C = None
+        if self.csw != 0.0:
+            from .clover import clover_matrix
+            self.C = clover_matrix(U, lat, self.csw)
         V = lat.V
         fwd, fs, bwd, bs = lat.tables()
         n = np.arange(V)
@@ -250,8 +256,16 @@ class WilsonOp:
     def hop_b(self, psi, mu):
         return self._mv(self.B[mu], psi)
 
-    def D(self, psi):
+    def site(self, psi):
+        """The site-local part of D: (4 + m0) psi, plus C psi with the clover term."""
         y = (4.0 + self.m0) * psi
+        if self.C is not None:
+            from .clover import apply_clover
+            y = y + apply_clover(self.C, psi)
+        return y
+
+    def D(self, psi):
+        y = self.site(psi)
         for mu in range(4):
             y = y - 0.5 * (self.hop_f(psi, mu) + self.hop_b(psi, mu))
         return y

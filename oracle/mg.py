@@ -173,7 +173,7 @@ def coarse_operator(op: WilsonOp, ag: Aggregation, P, chunk: int = 8):
     for c0 in range(0, n, chunk):
         cols = cols_all[c0:c0 + chunk]
         parts = []
-        self_part = (4.0 + op.m0) * cols
+        self_part = op.site(cols)
         for mu in range(4):
             F = op.hop_f(cols, mu)
             B = op.hop_b(cols, mu)
@@ -222,7 +222,7 @@ def apply_Dsigma(op: WilsonOp, sigma, psi):
 def apply_Dsigma_blocks(op: WilsonOp, ag: Aggregation, sigma, psi):
     """Block-diagonal part of D_sigma: hops that leave a block are dropped
     (Dirichlet block boundary)."""
-    y = (4.0 + op.m0) * psi - sigma * gamma5(psi)
+    y = op.site(psi) - sigma * gamma5(psi)
     for mu in range(4):
         y = y - 0.5 * (op.hop_f(psi, mu) * ag.int_fwd[mu]
                        + op.hop_b(psi, mu) * ag.int_bwd[mu])
