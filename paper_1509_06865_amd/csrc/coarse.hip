@@ -260,6 +260,114 @@ __global__ void __launch_bounds__(512) k_coarse_apply_mfma(CoarseGeom cg, const 
   }
 }
 
+// The same contraction on bfloat16 operands with FP32 accumulation
+// (v_mfma_f32_16x16x16bf16_1k): the blocks as stored in bfloat16, the fields
+// rounded to bfloat16 when staged.  Lane l holds A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16], i = 0..3, and the accumulator layout of the FP32
+// kernel above, so one MFMA covers 8 complex columns: in the interleaved
+// embedding a lane's four k entries are (Re, Im) of two adjacent complex
+// columns.  A 32-bit LDS word holds one complex entry (Re in the low half).
+constexpr int kMfmaPre16 = kMfmaMaxN2 / 32;   // 16-byte block loads per thread: n2^2 / 4 / (8 n2)
+
+__device__ inline unsigned bf16_pair(float re, float im) {
+  return (unsigned)to_bf16(re) | ((unsigned)to_bf16(im) << 16);
+}
+
+__global__ void __launch_bounds__(512) k_coarse_apply_mfma_bf16(CoarseGeom cg, const bf16c *__restrict__ Qc,
+                                                                const c64 *__restrict__ xin, c64 *__restrict__ yout,
+                                                                Shifts sig, const double *__restrict__ dsig,
+                                                                bool g5form, int nrhs) {
+  typedef short v4s __attribute__((ext_vector_type(4)));
+  __shared__ unsigned blk[kMfmaMaxN2 * (kMfmaMaxN2 + 1)];
+  __shared__ unsigned xs[kMfmaMaxN2 * (kMfmaRhs + 1)];
+  const int A = blockIdx.x, k0 = blockIdx.y * kMfmaRhs;
+  const int n2 = cg.n2, ld = n2 + 1, ldx = kMfmaRhs + 1;
+  const int kc = (nrhs - k0 < kMfmaRhs) ? nrhs - k0 : kMfmaRhs;
+  const int t = threadIdx.x, nthr = blockDim.x;
+  const int lane = t & 63, w = t >> 6;
+  const int n16 = n2 * n2 / 4;                                 // 16-byte groups per block (n2 % 8 == 0)
+  int nb[9];
+  nb[0] = A;
+  for (int mu = 0; mu < 4; ++mu) { nb[1 + mu] = cnbr(cg, A, mu, 1); nb[5 + mu] = cnbr(cg, A, mu, -1); }
+  const long long bs = (long long)n2 * n2;
+  auto block_ptr = [&](int d) -> const uint4 * {
+    const bf16c *p = (d < 5) ? Qc + ((long long)A * 5 + d) * bs : Qc + ((long long)nb[d] * 5 + (d - 4)) * bs;
+    return reinterpret_cast<const uint4 *>(p);
+  };
+  const int ci = 8 * w + ((lane & 15) >> 1), ri = lane & 1;    // A row: complex row, Re/Im
+  const int kq = lane >> 4;                                   // columns 2 kq, 2 kq + 1 of each group of 8
+  const int col = lane & 15;
+  uint4 pre[kMfmaPre16];
+#pragma unroll
+  for (int q = 0; q < kMfmaPre16; ++q) {
+    const int u = t + nthr * q;
+    pre[q] = (u < n16) ? block_ptr(0)[u] : make_uint4(0, 0, 0, 0);
+  }
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int d = 0; d < 9; ++d) {
+    __syncthreads();                                    // the previous block's reads are done
+#pragma unroll
+    for (int q = 0; q < kMfmaPre16; ++q) {
+      const int u = t + nthr * q;
+      if (u < n16) {
+        const int e = 4 * u, r = e / n2, cc = e - r * n2;         // 4 entries of one row
+        unsigned *dst = blk + r * ld + cc;
+        dst[0] = pre[q].x;
+        dst[1] = pre[q].y;
+        dst[2] = pre[q].z;
+        dst[3] = pre[q].w;
+      }
+    }
+    for (int e = t; e < kMfmaRhs * n2; e += nthr) {
+      const int k = e / n2, j = e - k * n2;
+      unsigned v = 0;
+      if (k < kc) {
+        const c64 xv = xin[((long long)(k0 + k) * cg.nA + nb[d]) * n2 + j];
+        v = bf16_pair(xv.re, xv.im);
+      }
+      xs[j * ldx + k] = v;
+    }
+    __syncthreads();
+    if (d + 1 < 9) {
+      const uint4 *M = block_ptr(d + 1);
+#pragma unroll
+      for (int q = 0; q < kMfmaPre16; ++q) {
+        const int u = t + nthr * q;
+        pre[q] = (u < n16) ? M[u] : make_uint4(0, 0, 0, 0);
+      }
+    }
+    // backward blocks are conjugate transposes: entry (i, j) = conj of stored (j, i)
+    const bool back = d >= 5;
+    const unsigned imflip = back ? 0x80000000u : 0u;
+    for (int s = 0; s < n2 / 8; ++s) {
+      const int cj = 8 * s + 2 * kq;
+      unsigned m0 = back ? blk[cj * ld + ci] : blk[ci * ld + cj];
+      unsigned m1 = back ? blk[(cj + 1) * ld + ci] : blk[ci * ld + cj + 1];
+      m0 ^= imflip;
+      m1 ^= imflip;
+      // Re row: (Mr, -Mi); Im row: (Mi, Mr)
+      const unsigned a0 = ri ? ((m0 >> 16) | (m0 << 16)) : (m0 ^ 0x80000000u);
+      const unsigned a1 = ri ? ((m1 >> 16) | (m1 << 16)) : (m1 ^ 0x80000000u);
+      const unsigned b0 = xs[cj * ldx + col], b1 = xs[(cj + 1) * ldx + col];
+      v4s a, b;
+      a[0] = (short)(a0 & 0xffffu); a[1] = (short)(a0 >> 16); a[2] = (short)(a1 & 0xffffu); a[3] = (short)(a1 >> 16);
+      b[0] = (short)(b0 & 0xffffu); b[1] = (short)(b0 >> 16); b[2] = (short)(b1 & 0xffffu); b[3] = (short)(b1 >> 16);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+  }
+  if (col < kc) {
+    const float sg = (float)(dsig ? dsig[k0 + col] : sig.s[k0 + col]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int crow = 8 * w + 2 * kq + h;
+      const long long off = ((long long)(k0 + col) * cg.nA + A) * n2 + crow;
+      c64 v = mk<float>(acc[2 * h], acc[2 * h + 1]) - sg * xin[off];
+      if (g5form && crow >= n2 / 2) v = -v;
+      yout[off] = v;
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_coarse_g5(CoarseGeom cg, const cplx<T> *__restrict__ x, cplx<T> *__restrict__ y, long long n) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -278,12 +386,19 @@ __global__ void k_set_shifts(Shifts s, int n, double *dst) {
 // workgroup per site with the blocks staged in LDS for 4, 8 or 16 rhs per pass;
 // 4, 5 = as 1, 2 with one workgroup per (site, chunk of 4 or 8 rhs), for
 // coarse grids too small to fill the GPU with one workgroup per site; 6 = the
-// matrix-core kernel (FP32 arithmetic only, 2Nv a multiple of 8 up to 64).
-constexpr int kCoarseVariants = 7;
+// matrix-core kernel (FP32 arithmetic only, 2Nv a multiple of 8 up to 64);
+// 7 = the matrix-core kernel on bfloat16 operands (bfloat16 storage only, same
+// block sizes; the fields are rounded to bfloat16 as well).
+constexpr int kCoarseVariants = 8;
 constexpr int kCoarseMfma = 6;
+constexpr int kCoarseMfmaBf16 = 7;
 
 template <typename T> bool mfma_applies(const CoarseGeom &cg) {
   return sizeof(T) == 4 && cg.n2 % 8 == 0 && cg.n2 <= kMfmaMaxN2;
+}
+
+template <typename T, typename QT> bool mfma_bf16_applies(const CoarseGeom &cg) {
+  return std::is_same<QT, bf16c>::value && mfma_applies<T>(cg);
 }
 
 template <typename T, typename QT>
@@ -310,6 +425,16 @@ void coarse_launch_variant(int v, KTimerScope &kt, const CoarseGeom &cg, const Q
       LQ_LAUNCH(kt, (k_coarse_apply_multi<T, QT, 8>), dim3(cg.nA, (nrhs + 7) / 8), dim3(256), 0, st, cg, Qc, x, y,
                 sig, dsig, g5form, nrhs);
       break;
+    case kCoarseMfmaBf16:
+      if constexpr (std::is_same<T, float>::value && std::is_same<QT, bf16c>::value) {
+        if (mfma_bf16_applies<T, QT>(cg)) {
+          LQ_LAUNCH(kt, k_coarse_apply_mfma_bf16, dim3(cg.nA, (nrhs + kMfmaRhs - 1) / kMfmaRhs),
+                    dim3(64 * (cg.n2 / 8)), 0, st, cg, Qc, x, y, sig, dsig, g5form, nrhs);
+          break;
+        }
+      }
+      // not applicable: as kernel 6
+      [[fallthrough]];
     case kCoarseMfma:
       if constexpr (std::is_same<T, float>::value) {
         if (mfma_applies<T>(cg)) {
@@ -394,6 +519,7 @@ int tune_coarse_apply_q(const CoarseGeom &cg, const QT *Qc, const cplx<T> *x, cp
   float tbest = 1e30f;
   for (int v = 0; v < kCoarseVariants; ++v) {
     if (v == kCoarseMfma && !mfma_applies<T>(cg)) continue;
+    if (v == kCoarseMfmaBf16 && !mfma_bf16_applies<T, QT>(cg)) continue;
     coarse_launch_variant<T, QT>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);
     LQ_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 3; ++r) coarse_launch_variant<T, QT>(v, off, cg, Qc, x, y, z, nullptr, nrhs, true, st);

@@ -293,14 +293,16 @@ def coarse_kernel():
     coarse_variant(-1)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("prec,tol,bf16", [(0, 1e-12, 0), (1, 3e-6, 0), (1, 1e-2, 1)], ids=["fp64", "fp32", "bf16"])
 def test_coarse_apply_many_sites(prec, tol, bf16, variant, coarse_kernel):
-    # 8192 coarse sites, each of the six coarse-apply kernels (one wave per
+    # 8192 coarse sites, each of the coarse-apply kernels (one wave per
     # (site, rhs); LDS-staged blocks for 4, 8, 16 rhs per pass, per site or
-    # per (site, chunk of 4 or 8 rhs)), FP64, FP32, or FP32 arithmetic on a
-    # bfloat16 copy of Q_c (entries rounded to 2^-9 relative); 11 rhs leave a
-    # ragged chunk
+    # per (site, chunk of 4 or 8 rhs); matrix cores in FP32; matrix cores on
+    # bfloat16 operands, which falls back to the FP32 matrix-core kernel
+    # without bfloat16 storage), FP64, FP32, or FP32 arithmetic on a bfloat16
+    # copy of Q_c (entries rounded to 2^-9 relative); 11 rhs leave a ragged
+    # chunk
     coarse_kernel(variant)
     dims, agg = (16, 16, 16, 32), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 31)
@@ -325,13 +327,17 @@ def test_coarse_apply_many_sites(prec, tol, bf16, variant, coarse_kernel):
         assert relmax(y, ref) > 1e-5          # the bfloat16 operator was the one applied
 
 
-@pytest.mark.parametrize("nv,variant", [(24, -1), (24, 6), (32, 6)], ids=["48-tuned", "48-mfma", "64-mfma"])
-def test_coarse_apply_galerkin_identity_full_blocks(nv, variant, coarse_kernel):
+@pytest.mark.parametrize("nv,variant,bf16,tol", [(24, -1, 0, 2e-5), (24, 6, 0, 2e-5), (32, 6, 0, 2e-5),
+                                                  (24, 7, 1, 1e-2), (32, 7, 1, 1e-2)],
+                         ids=["48-tuned", "48-mfma", "64-mfma", "48-mfma-bf16", "64-mfma-bf16"])
+def test_coarse_apply_galerkin_identity_full_blocks(nv, variant, bf16, tol, coarse_kernel):
     # 4096 coarse sites with 48 x 48 blocks (Nv = 24) or 64 x 64 (Nv = 32, the
-    # 32^3 x 64 workload's), mixed precision, the tuned kernel or the
-    # matrix-core one: the coarse apply equals P^dag (Q - sigma) P x, the
-    # Galerkin identity of sec. 2, formed from the prolongation, the FP64 Q
-    # apply and the restriction (each pinned to the oracle on small cases).
+    # 32^3 x 64 workload's), mixed precision, the tuned kernel, the FP32
+    # matrix-core one, or the matrix-core one on bfloat16 operands (bfloat16
+    # copy of Q_c, fields rounded to bfloat16: both at 2^-9 relative): the
+    # coarse apply equals P^dag (Q - sigma) P x, the Galerkin identity of
+    # sec. 2, formed from the prolongation, the FP64 Q apply and the
+    # restriction (each pinned to the oracle on small cases).
     coarse_kernel(variant)
     dims, agg = (16, 16, 16, 16), (2, 2, 2, 2)
     U = lqsynth.gauge_field(dims, 0.25, 41)
@@ -339,7 +345,7 @@ def test_coarse_apply_galerkin_identity_full_blocks(nv, variant, coarse_kernel):
     c = _ctx(dims, 1)
     Ud = dev(U)
     c.mg_setup(Ud, -0.15, agg, dev(lqsynth.gaussian_spinors(nv, dims, 42)),
-               MGParams(precision=1, n_setup=0, n_init=1))
+               MGParams(precision=1, n_setup=0, n_init=1, coarse_bf16=bf16))
     nA = 8 ** 3 * 8
     rng = np.random.default_rng(43)
     nr = 9
@@ -349,7 +355,9 @@ def test_coarse_apply_galerkin_identity_full_blocks(nv, variant, coarse_kernel):
     for k in (0, 4, 8):
         f = c.prolong(dev(x[k:k + 1]))
         ref = host(c.restrict(c.q_apply(Ud, -0.15, f)))[0] - sig[k] * x[k]
-        assert relmax(y[k], ref) < 2e-5
+        assert relmax(y[k], ref) < tol
+        if bf16:
+            assert relmax(y[k], ref) > 1e-5        # bfloat16 rounding is present
 
 
 def test_argument_and_state_errors_are_reported():

@@ -56,12 +56,12 @@ def test_create_rejects_bad_arguments():
 
 
 def test_coarse_variant_switch_checks_its_argument():
-    # host-only: forcing a coarse-apply kernel accepts -1 (tuned) and 0..6
+    # host-only: forcing a coarse-apply kernel accepts -1 (tuned) and 0..7
     from paper_1509_06865_amd.lqmg import LQError, coarse_variant
-    for v in (-2, 7, 100):
+    for v in (-2, 8, 100):
         with pytest.raises(LQError):
             coarse_variant(v)
-    for v in range(7):
+    for v in range(8):
         coarse_variant(v)
     coarse_variant(-1)
 
