@@ -136,7 +136,23 @@ int lq_create(lq_ctx **out, const int dims[4], int t_bc, void *hip_stream);
 int lq_destroy(lq_ctx *ctx);
 const char *lq_last_error(const lq_ctx *ctx);
 
-/* y = Q x for n_rhs fields (sec. 2: Q = gamma5 D).  U: device [4][9][V];
+/* Clover term (sec. 2: the operator is the clover-improved Wilson operator):
+ * from this call on, D = (4 + m0) + C(x) - 1/2 sum_mu (hops) in every operator
+ * application of the context (q_apply, q_apply_c64, the multigrid, the
+ * solves, RQI, the Krylov solver, LMA), with
+ *   C(x) = csw (i/4) sum_{mu != nu} sigma_munu (x) F_munu(x),
+ *   F_munu = (Q_munu - Q_munu^dag) / 8, Q_munu the four plaquettes of the
+ *   mu-nu plane at x (all starting with +mu, then +nu), sigma_munu =
+ *   (i/2)[gamma_mu, gamma_nu] in the chiral basis.
+ * C is built from U (device [4][9][V] canonical FP64, the links the later
+ * calls pass; gauge loops take no boundary sign) and held by the context.
+ * csw = 0 returns to the plain Wilson operator (U may then be NULL).  The
+ * hierarchy of an earlier mg_setup is dropped: call mg_setup afterwards.
+ * Synchronous.  Errors: LQ_ERR_ARG, LQ_ERR_OOM. */
+int lq_clover(lq_ctx *ctx, const lq_c128 *U, double csw);
+
+/* y = Q x for n_rhs fields (sec. 2: Q = gamma5 D, with the clover term of
+ * lq_clover if one is set).  U: device [4][9][V];
  * x, y: device [n_rhs][12][V], must not overlap.  Asynchronous.
  * Errors: LQ_ERR_ARG (NULL pointer, n_rhs < 1). */
 int q_apply(lq_ctx *ctx, const lq_c128 *U, double m0, const lq_c128 *x,
@@ -251,6 +267,29 @@ int lma_high(lq_ctx *ctx, const lq_c128 *U, double m0, int n, const lq_c128 *V, 
  * estimators.  Errors: LQ_ERR_ARG. */
 int lq_timeslice_products(lq_ctx *ctx, int nb, const lq_c128 *E, int nw, const lq_c128 *W, lq_c128 *out);
 
+/* ---- restarted Krylov eigensolver (the comparison of sec. 2.2) -------------- */
+/* The n_eig eigenpairs of Q of smallest |lambda| by a restarted Lanczos
+ * method on Q^2, the kind of solver the paper compares RQI with multigrid
+ * against (sec. 2.2: a Krylov space of n_kv vectors, restarted from the
+ * current approximations).  Each cycle extends the basis to n_kv vectors,
+ * orthogonalising every new vector twice against the whole basis; the n_kv
+ * x n_kv projected matrix gives Ritz pairs of Q^2, and the basis restarts from
+ * the lowest Ritz vectors plus the last Lanczos vector.  A Ritz pair of Q^2
+ * counts as converged when its residual is below tol * 2 sqrt(theta) (which
+ * bounds the residual of Q by about tol); when the n_eig + n_guard lowest have
+ * converged (or after max_restarts restarts), a Rayleigh-Ritz step with Q on
+ * those n_eig + n_guard vectors separates pairs +-lambda, and the n_eig of
+ * smallest |lambda| are returned.  U: device links [4][9][V] canonical as for
+ * q_apply; v0: device start vector [12][V] (nonzero); V: device output
+ * [n_eig][12][V] canonical; lambda, resid: host double[n_eig] (eigenvalues in
+ * increasing |lambda|, residuals ||Q v - lambda v|| of the unit vectors);
+ * info (nullable): host int[3] = restarts, Q^2 products, converged (0/1).
+ * Needs no hierarchy; allocates 2 (n_kv + 1) + 16 fields.
+ * n_eig + n_guard + 16 <= n_kv <= 191.  Errors: LQ_ERR_ARG, LQ_ERR_NUMERIC
+ * (the Krylov space became invariant), LQ_ERR_OOM. */
+int lanczos_lowmodes(lq_ctx *ctx, const lq_c128 *U, double m0, int n_eig, int n_guard, int n_kv, double tol,
+                     int max_restarts, const lq_c128 *v0, double *lambda, lq_c128 *V, double *resid, int *info);
+
 /* ---- learned setup: network layer (not part of the paper) ------------------- */
 /* One parallel-transport convolution of the network that proposes multigrid
  * test vectors:  out[o](x) = sum_{i < c_in} sum_{d in {-1,0,1}^4}
@@ -323,19 +362,22 @@ int lq_adam_step(lq_ctx *ctx, long long n, double *p, const double *g, double *m
 int lq_herm_eigh(int n, const lq_c128 *A, double *w, lq_c128 *V);
 
 /* ---- coarse-apply kernel choice --------------------------------------------- */
-/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has seven
+/* The coarse operator apply (sec. 2's Q_c acting on coarse vectors) has eight
  * kernels: 0 one wavefront per (coarse site, rhs); 1, 2, 3 one workgroup per
  * coarse site with each 2Nv x 2Nv block staged in LDS and applied to 4, 8 or
  * 16 right-hand sides per pass; 4, 5 as 1, 2 with one workgroup per (coarse
  * site, chunk of 4 or 8 right-hand sides); 6 the matrix-core kernel (FP32
  * arithmetic on FP32 or bfloat16 storage, one workgroup per (coarse site,
  * 16 right-hand sides), 2Nv a multiple of 8 up to 64; where it does not apply
- * kernel 2 runs instead).  By default each coarse solve times the applicable
- * kernels on its first call for a shape (precision, coarse sites, 2Nv, rhs
- * count, device) and keeps the fastest for the process.
- * lq_coarse_variant(v) with v in 0..6 forces kernel v for every shape (tests
+ * kernel 2 runs instead); 7 the matrix-core kernel on bfloat16 operands with
+ * FP32 accumulation (bfloat16 storage only, i.e. coarse_bf16 = 1; the fields
+ * are rounded to bfloat16 inside the kernel; same block sizes as 6; where it
+ * does not apply kernel 6 runs instead).  By default each coarse solve times
+ * the applicable kernels on its first call for a shape (precision, storage,
+ * coarse sites, 2Nv, rhs count, device) and keeps the fastest for the process.
+ * lq_coarse_variant(v) with v in 0..7 forces kernel v for every shape (tests
  * compare them); v = -1 returns to the tuned choice.  Process-wide, not
- * thread-safe.  Errors: LQ_ERR_ARG for v outside -1..6. */
+ * thread-safe.  Errors: LQ_ERR_ARG for v outside -1..7. */
 int lq_coarse_variant(int v);
 
 /* ---- kernel timing (measurement of the hot kernels against the roofline) -- */

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "liblqmg.so")
-SOURCES = ["wilson.hip", "blas.hip", "sap.hip", "transfer.hip", "coarse.hip", "gram.hip", "ptc.hip", "level2.hip", "ktimer.cpp",
+SOURCES = ["wilson.hip", "blas.hip", "sap.hip", "transfer.hip", "coarse.hip", "gram.hip", "ptc.hip", "level2.hip", "clover.hip", "ktimer.cpp",
            "lqmg_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -128,4 +128,8 @@ __device__ inline int xcd_tile(int b, int n) {
 // Per-rhs scalar passed to kernels: shifts, coefficients.
 constexpr int kMaxRhs = 16;
 
+// Rows of a stored clover field [kCloverRows][V] (42 used; a multiple of 12,
+// so the layout changes of [n][12][V] fields apply to it).
+constexpr int kCloverRows = 48;
+
 }  // namespace lq

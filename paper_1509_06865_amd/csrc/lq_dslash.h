@@ -92,4 +92,35 @@ __device__ inline void hop(int mu, bool fwd, const cplx<T> p[12], const cplx<T> 
   hop_link(mu, fwd, p, m, sign, acc);
 }
 
+// Clover term (site-local, commutes with gamma5): per site two Hermitian 6 x 6
+// blocks, one per chirality (components 6b .. 6b + 5 = spins 2b, 2b + 1 times
+// colour).  Stored [48][V] (42 used): block b at rows 21 b .. 21 b + 20, the
+// six diagonal entries (real, held in .re) first, then the upper triangle
+// (k, l), k < l, row by row (kCloverRows in lq_common.h).
+
+// acc += scale * C(s) p
+template <typename T>
+__device__ inline void clover_add(const cplx<T> *__restrict__ C, long long V, int s, const cplx<T> p[12], T scale,
+                                  cplx<T> acc[12]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const cplx<T> *Cb = C + (long long)(21 * b) * V + s;
+    cplx<T> y[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = Cb[(long long)k * V].re * p[6 * b + k];
+    int q = 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int l = k + 1; l < 6; ++l) {
+        const cplx<T> m = Cb[(long long)q * V];
+        y[k] = y[k] + m * p[6 * b + l];
+        y[l] = y[l] + cmul_conj(m, p[6 * b + k]);
+        ++q;
+      }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[6 * b + k] = acc[6 * b + k] + scale * y[k];
+  }
+}
+
 }  // namespace lq

@@ -11,18 +11,23 @@ struct Shifts { double s[kMaxRhs]; };
 
 // ---- Wilson stencil (wilson.hip) -------------------------------------------
 enum WilsonMode { W_QSHIFT = 0, W_RESID = 1 };
-// mode W_QSHIFT: y_k = (Q - sigma_k) x_k ; W_RESID: y_k = b_k - (Q - sigma_k) x_k
+// mode W_QSHIFT: y_k = (Q - sigma_k) x_k ; W_RESID: y_k = b_k - (Q - sigma_k) x_k.
+// C: the clover term [kCloverRows][V] in the layout of U (nullptr: none).
 template <typename T>
 void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y,
                    const cplx<T> *b, double m0, const Shifts &sig, int nrhs, int mode,
-                   hipStream_t st);
+                   hipStream_t st, const cplx<T> *C = nullptr);
 // Split hops of Q for the coarse operator.  Input: nf fields x (one column of
 // P each) whose gamma5 half 'half[j]' is used (the other half read as zero).
-// Output parts[j][5][12][V]: part 0 = gamma5[(4+m0) x - 1/2 sum_mu (hops that
+// Output parts[j][5][12][V]: part 0 = gamma5[((4+m0) + C) x - 1/2 sum_mu (hops that
 // stay inside a block)], part 1+mu = gamma5[-1/2 (forward mu hop leaving the block)].
 template <typename T>
 void launch_coarse_parts(const Geom &g, const cplx<T> *U, const cplx<T> *x, const int *half_dev,
-                         int nf, long long xstride, cplx<T> *parts, double m0, hipStream_t st);
+                         int nf, long long xstride, cplx<T> *parts, double m0, hipStream_t st,
+                         const cplx<T> *C = nullptr);
+// Clover term of the FP64 links U (canonical or blocked, as g says) into
+// C [kCloverRows][V] (clover.hip).
+void launch_clover_build(const Geom &g, const c128 *U, double csw, c128 *C, hipStream_t st);
 
 // ---- BLAS-1 (blas.hip) ------------------------------------------------------
 // Batched vectors: nrhs vectors of length n, vector k at base + k*stride.
@@ -87,7 +92,7 @@ void launch_pack_links(const Geom &blocked, const c128 *U, cplx<To> *out, hipStr
 template <typename T>
 void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T> *z,
                        const int *blocks_of_colour, int nblocks, double m0, const Shifts &sig,
-                       int nrhs, int n_mr, hipStream_t st);
+                       int nrhs, int n_mr, hipStream_t st, const cplx<T> *C = nullptr);
 
 // ---- transfers (transfer.hip) -----------------------------------------------
 // c[j][A][h*Nv + k] = sum_{x in A, s in h, col} conj(P_k[3s+col][x]) f_j[3s+col][x]

@@ -76,6 +76,7 @@ bool verbose() {
 
 template <typename T> struct MGData {
   DevBuf<cplx<T>> U;    // blocked links (T precision)
+  DevBuf<cplx<T>> C;    // blocked clover term (T precision), when c_sw != 0
   DevBuf<cplx<T>> P;    // [Nv][12][V]
   DevBuf<cplx<T>> Qc;   // [nA][5][n2][n2]
   DevBuf<cplx<T>> P2;   // third level: [Nv2][nA][n2]
@@ -133,6 +134,9 @@ struct lq_ctx {
   Geom g;
   CoarseGeom cg;
   DevBuf<c128> U64;                 // blocked FP64 links (outer operator)
+  double csw = 0;                   // clover coefficient (lq_clover); 0: plain Wilson
+  DevBuf<c128> clov_can, clov64;    // clover term: canonical (from lq_clover), blocked (mg_setup)
+  DevBuf<c64> clov_can32;           // canonical FP32 copy (q_apply_c64)
   MGData<double> d64;
   MGData<float> d32;
   DevBuf<c128> W;                   // test vectors, blocked, FP64
@@ -175,6 +179,7 @@ struct lq_ctx {
   DevBuf<c64> parts2_32, pc2_32;
   DevBuf<c128> lma_V, lma_W, lma_X;  // approximate low-mode averaging: kept vectors, work fields
   DevBuf<c128> lma_out;
+  DevBuf<c128> lz_basis[2], lz_tmp;  // restarted Lanczos: the basis and its restarted copy, Q v
   int coarse_iters = 0;
   // captured coarse-GMRES chunks, keyed by shape, step range and every pointer
   // they use; cap_st is the private stream they are captured on
@@ -512,6 +517,14 @@ bool gmres_batched(lq_ctx *c, KrylovWork<T> &kw, long long n, int nrhs, const KO
 template <typename T> MGData<T> &mgd(lq_ctx *c);
 template <> MGData<double> &mgd<double>(lq_ctx *c) { return c->d64; }
 template <> MGData<float> &mgd<float>(lq_ctx *c) { return c->d32; }
+// The clover term to pass with the links (nullptr without one): canonical
+// FP64 / FP32 for the caller's links, blocked FP64 for the outer operator,
+// blocked in the multigrid's precision.
+const c128 *clov_can(lq_ctx *c) { return c->csw != 0 ? c->clov_can.p : nullptr; }
+const c64 *clov_can32(lq_ctx *c) { return c->csw != 0 ? c->clov_can32.p : nullptr; }
+const c128 *clov_blk(lq_ctx *c) { return c->csw != 0 ? c->clov64.p : nullptr; }
+template <typename T> const cplx<T> *clov_mg(lq_ctx *c) { return c->csw != 0 ? mgd<T>(c).C.p : nullptr; }
+
 template <typename T> KrylovWork<T> &ckw(lq_ctx *c);
 template <> KrylovWork<double> &ckw<double>(lq_ctx *c) { return c->coarse_kw64; }
 template <> KrylovWork<float> &ckw<float>(lq_ctx *c) { return c->coarse_kw32; }
@@ -530,7 +543,7 @@ void sap(lq_ctx *c, const double *sig, const cplx<T> *r, cplx<T> *z, int nrhs, i
     for (int col = 0; col < 2; ++col)
       if (c->nblocks[col] > 0)
         launch_sap_colour<T>(c->g, mgd<T>(c).U.p, r, z, c->blocks[col].p, c->nblocks[col], c->m0, S, nrhs,
-                             c->p.sap_mr, c->st);
+                             c->p.sap_mr, c->st, clov_mg<T>(c));
 }
 
 // Restarted GMRES for (Q_c - sigma) e = c on one coarse level (the operator
@@ -713,7 +726,7 @@ void cycle(lq_ctx *c, const double *sig, const cplx<T> *r, cplx<T> *z, int nrhs)
   const cplx<T> *rr = r;
   if (c->p.pre > 0) {
     sap<T>(c, sig, r, z, nrhs, c->p.pre);
-    launch_wilson<T>(c->g, d.U.p, z, b.tmp, r, c->m0, shifts_of(sig, nrhs), nrhs, W_RESID, c->st);
+    launch_wilson<T>(c->g, d.U.p, z, b.tmp, r, c->m0, shifts_of(sig, nrhs), nrhs, W_RESID, c->st, clov_mg<T>(c));
     rr = b.tmp;
   }
   launch_restrict<T>(c->g, d.P.p, c->Nv, rr, 12LL * c->g.V, nrhs, b.rc, c->st);
@@ -766,7 +779,7 @@ template <typename T> void build_coarse(lq_ctx *c, DevBuf<cplx<T>> &parts, DevBu
       std::vector<int> hi(2 * C);
       for (int j = 0; j < nc; ++j) { hi[j] = h; hi[C + j] = h * Nv + l0 + j; }
       LQ_HIP(hipMemcpyAsync(dint, hi.data(), 2 * C * sizeof(int), hipMemcpyHostToDevice, c->st));
-      launch_coarse_parts<T>(c->g, d.U.p, d.P.p + l0 * V12, dint, nc, V12, pa, c->m0, c->st);
+      launch_coarse_parts<T>(c->g, d.U.p, d.P.p + l0 * V12, dint, nc, V12, pa, c->m0, c->st, clov_mg<T>(c));
       launch_restrict<T>(c->g, d.P.p, Nv, pa, V12, 5 * nc, pcb, c->st);
       launch_scatter_coarse<T>(pcb, nc, dint + C, n2, nA, Qc, c->st);
       sync(c);
@@ -893,14 +906,14 @@ bool solve_shifted(lq_ctx *c, int nrhs, const double *sig, const c128 *b, c128 *
   std::vector<double> sv(sig, sig + nrhs);
   KOps<double> ops;
   ops.apply = [=](const c128 *in, c128 *out) {
-    launch_wilson<double>(c->g, c->U64.p, in, out, nullptr, c->m0, S, nrhs, W_QSHIFT, c->st);
+    launch_wilson<double>(c->g, c->U64.p, in, out, nullptr, c->m0, S, nrhs, W_QSHIFT, c->st, clov_blk(c));
   };
   if (D)
     ops.precond = [=](const c128 *in, c128 *out) { deflated_precond(c, *D, sv.data(), in, out, nrhs); };
   else
     ops.precond = [=](const c128 *in, c128 *out) { precond64(c, sv.data(), in, out, nrhs); };
   ops.resid = [=](const c128 *bb, const c128 *xx, c128 *r) {
-    launch_wilson<double>(c->g, c->U64.p, xx, r, bb, c->m0, S, nrhs, W_RESID, c->st);
+    launch_wilson<double>(c->g, c->U64.p, xx, r, bb, c->m0, S, nrhs, W_RESID, c->st, clov_blk(c));
   };
   return gmres_batched<double>(c, c->fine_kw, n, nrhs, ops, b, x, c->p.fgmres_m, max_restarts, tol, iters, relres,
                                1);
@@ -1064,7 +1077,7 @@ void rayleigh_ritz_tail(lq_ctx *c, c128 *E, int n, int L, std::vector<double> &l
   Shifts z = shifts_of(nullptr, 0);
   for (int j0 = 0; j0 < m; j0 += kMaxRhs) {
     const int nk = std::min(kMaxRhs, m - j0);
-    launch_wilson<double>(c->g, c->U64.p, EU + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+    launch_wilson<double>(c->g, c->U64.p, EU + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st, clov_blk(c));
     auto a = gram(c, m, EU, V12, nk, QE, V12, V12);
     auto g = gram(c, m, EU, V12, nk, EU + j0 * V12, V12, V12);
     for (int i = 0; i < m; ++i)
@@ -1206,7 +1219,7 @@ void projected_operator(lq_ctx *c, const c128 *E, int n, std::vector<cd> &A, std
   Shifts z = shifts_of(nullptr, 0);
   for (int j0 = 0; j0 < n; j0 += kMaxRhs) {
     const int nk = std::min(kMaxRhs, n - j0);
-    launch_wilson<double>(c->g, c->U64.p, E + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+    launch_wilson<double>(c->g, c->U64.p, E + j0 * V12, QE, nullptr, c->m0, z, nk, W_QSHIFT, c->st, clov_blk(c));
     auto a = gram(c, n, E, V12, nk, QE, V12, V12);
     auto g = gram(c, n, E, V12, nk, E + j0 * V12, V12, V12);
     for (int i = 0; i < n; ++i)
@@ -1225,7 +1238,8 @@ void update_projected(lq_ctx *c, const c128 *E, int n, const std::vector<int> &i
   const long long V12 = 12LL * c->g.V;
   const int nk = (int)ids.size();
   c128 *QX = idle_fields(c);
-  launch_wilson<double>(c->g, c->U64.p, X, QX, nullptr, c->m0, shifts_of(nullptr, 0), nk, W_QSHIFT, c->st);
+  launch_wilson<double>(c->g, c->U64.p, X, QX, nullptr, c->m0, shifts_of(nullptr, 0), nk, W_QSHIFT, c->st,
+                        clov_blk(c));
   auto a = gram(c, n, E, V12, nk, QX, V12, V12);
   auto g = gram(c, n, E, V12, nk, X, V12, V12);
   for (int q = 0; q < nk; ++q) {
@@ -1251,7 +1265,7 @@ void deflated_precond(lq_ctx *c, const Deflation &D, const double *sig, const c1
   }
   c128 *U = c->defl_u.get((size_t)kMaxRhs * n), *R = c->defl_r.get((size_t)kMaxRhs * n);
   combine(c, D.n, D.E, n, nrhs, Y, 1.0, U, n, n, false);
-  launch_wilson<double>(c->g, c->U64.p, U, R, in, c->m0, shifts_of(sig, nrhs), nrhs, W_RESID, c->st);
+  launch_wilson<double>(c->g, c->U64.p, U, R, in, c->m0, shifts_of(sig, nrhs), nrhs, W_RESID, c->st, clov_blk(c));
   precond64(c, sig, R, out, nrhs);
   launch_multi_axpy<double>(1, U, 0, n, c->plus_one.p, out, n, n, nrhs, 1.0, c->st);
 }
@@ -1371,6 +1385,22 @@ int lq_destroy(lq_ctx *c) {
 
 const char *lq_last_error(const lq_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
 
+int lq_clover(lq_ctx *c, const lq_c128 *U, double csw) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if ((!U && csw != 0) || !std::isfinite(csw)) fail(LQ_ERR_ARG, "lq_clover: NULL links or c_sw not finite");
+    // a hierarchy built with the previous operator no longer matches it
+    c->have = false;
+    c->csw = csw;
+    if (csw == 0) return LQ_OK;
+    const long long CV = (long long)kCloverRows * c->gcan.V;
+    launch_clover_build(c->gcan, (const c128 *)U, csw, c->clov_can.get(CV), c->st);
+    launch_convert<float, double>(c->clov_can.p, c->clov_can32.get(CV), CV, c->st);
+    sync(c);
+    return LQ_OK;
+  });
+}
+
 int q_apply(lq_ctx *c, const lq_c128 *U, double m0, const lq_c128 *x, lq_c128 *y, int n_rhs) {
   return guard(c, [&] {
     check_ctx(c);
@@ -1380,7 +1410,7 @@ int q_apply(lq_ctx *c, const lq_c128 *U, double m0, const lq_c128 *x, lq_c128 *y
     for (int k0 = 0; k0 < n_rhs; k0 += kMaxRhs) {
       const int nk = std::min(kMaxRhs, n_rhs - k0);
       launch_wilson<double>(c->gcan, (const c128 *)U, (const c128 *)x + k0 * L, (c128 *)y + k0 * L, nullptr, m0, S,
-                            nk, W_QSHIFT, c->st);
+                            nk, W_QSHIFT, c->st, clov_can(c));
     }
     return LQ_OK;
   });
@@ -1395,7 +1425,7 @@ int q_apply_c64(lq_ctx *c, const lq_c64 *U, double m0, const lq_c64 *x, lq_c64 *
     for (int k0 = 0; k0 < n_rhs; k0 += kMaxRhs) {
       const int nk = std::min(kMaxRhs, n_rhs - k0);
       launch_wilson<float>(c->gcan, (const c64 *)U, (const c64 *)x + k0 * L, (c64 *)y + k0 * L, nullptr, m0, S, nk,
-                           W_QSHIFT, c->st);
+                           W_QSHIFT, c->st, clov_can32(c));
     }
     return LQ_OK;
   });
@@ -1477,6 +1507,13 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, int n_levels, const int n_t
     launch_pack_links<double>(c->g, (const c128 *)U, c->U64.get(36 * V), c->st);
     if (p.precision == LQ_PREC_FP64) copy<double>(c, c->d64.U.get(36 * V), c->U64.p, 36 * V);
     else launch_pack_links<float>(c->g, (const c128 *)U, c->d32.U.get(36 * V), c->st);
+    // the clover term of lq_clover in the blocked layout (rows as 4 fields of 12)
+    if (c->csw != 0) {
+      const long long CV = (long long)kCloverRows * V;
+      launch_permute<double>(c->g, c->clov_can.p, c->clov64.get(CV), kCloverRows / 12, true, c->st);
+      if (p.precision == LQ_PREC_FP64) copy<double>(c, c->d64.C.get(CV), c->clov64.p, CV);
+      else launch_convert<float, double>(c->clov64.p, c->d32.C.get(CV), CV, c->st);
+    }
     // red / black block lists
     std::vector<int> lists[2];
     for (int A = 0; A < c->g.nblk; ++A) {
@@ -1640,7 +1677,7 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         const int nk = (int)std::min<size_t>(kMaxRhs, ids.size() - q0);
         for (int q = 0; q < nk; ++q) copy<double>(c, B + q * V12, E + ids[q0 + q] * V12, V12);
         Shifts z = shifts_of(nullptr, 0);
-        launch_wilson<double>(c->g, c->U64.p, B, X, nullptr, c->m0, z, nk, W_QSHIFT, c->st);
+        launch_wilson<double>(c->g, c->U64.p, B, X, nullptr, c->m0, z, nk, W_QSHIFT, c->st, clov_blk(c));
         // all nk pairs at once: lambda_q = <v_q, Q v_q>, X_q <- Q v_q - lambda_q v_q, eps_q = |X_q|
         auto d = dots<double>(c, 1, B, 0, V12, X, V12, V12, nk);
         std::vector<cd> lq(nk);
@@ -2033,7 +2070,7 @@ LmaLow lma_prepare(lq_ctx *c, const c128 *U, double m0, int n, const c128 *V, co
   Shifts z = shifts_of(nullptr, 0);
   for (int j0 = 0; j0 < L.n; j0 += kMaxRhs) {
     const int nk = std::min(kMaxRhs, L.n - j0);
-    launch_wilson<double>(c->gcan, U, Vk + j0 * V12, QV, nullptr, m0, z, nk, W_QSHIFT, c->st);
+    launch_wilson<double>(c->gcan, U, Vk + j0 * V12, QV, nullptr, m0, z, nk, W_QSHIFT, c->st, clov_can(c));
     auto a = gram(c, L.n, Vk, V12, nk, QV, V12, V12);
     for (int i = 0; i < L.n; ++i)
       for (int k = 0; k < nk; ++k) L.A[(size_t)i * L.n + j0 + k] = a[(size_t)i * nk + k];
@@ -2043,6 +2080,164 @@ LmaLow lma_prepare(lq_ctx *c, const c128 *U, double m0, int n, const c128 *V, co
   return L;
 }
 
+
+// ---------------------------------------------------------------------------
+// Restarted Lanczos on Q^2 (the Krylov comparison of sec. 2.2): the n_eig
+// eigenvalues of Q of smallest modulus are the smallest of Q^2.  Each cycle
+// extends the basis to n_kv vectors; every new vector is orthogonalised
+// against the whole basis twice (so the projected matrix is formed from
+// inner products, not assumed tridiagonal), Rayleigh-Ritz on that matrix gives
+// the Ritz pairs of Q^2, and the basis restarts from the kk lowest Ritz
+// vectors plus the last Lanczos vector (thick restart).  The converged Ritz
+// vectors then get a Rayleigh-Ritz step with Q itself, which separates pairs
+// +-lambda that Q^2 cannot.  Canonical layout, the caller's FP64 links.
+// ---------------------------------------------------------------------------
+struct LanczosOut {
+  int restarts = 0;
+  long long matvecs = 0;
+  bool converged = false;
+};
+
+LanczosOut lanczos_q2(lq_ctx *c, const c128 *U, double m0, int n_eig, int n_want, int n_kv, double tol,
+                      int max_restarts, const c128 *v0, double *lam, c128 *Vout, double *resid) {
+  const long long V12 = 12LL * c->gcan.V;
+  const Shifts z = shifts_of(nullptr, 0);
+  c128 *B = c->lz_basis[0].get((size_t)(n_kv + 1) * V12);
+  c128 *B2 = c->lz_basis[1].get((size_t)(n_kv + 1) * V12);
+  c128 *tmp = c->lz_tmp.get((size_t)kMaxRhs * V12);
+  LanczosOut out;
+  auto at = [](std::vector<cd> &M, int n, int i, int j) -> cd & { return M[(size_t)i * n + j]; };
+  // first basis vector
+  copy<double>(c, B, v0, V12);
+  {
+    const double nv = norms<double>(c, B, V12, 1)[0];
+    if (!(nv > 0)) fail(LQ_ERR_ARG, "lanczos_lowmodes: the start vector is zero");
+    scale<double>(c, {cd(1.0 / nv)}, B, V12, B, V12, V12, 1, false);
+  }
+  std::vector<cd> T((size_t)n_kv * n_kv, cd(0));
+  std::vector<double> theta;
+  std::vector<cd> Z;
+  std::vector<int> ord;
+  double beta = 0;
+  int k = 0;                 // vectors carried over from the last restart
+  for (;;) {
+    for (int j = k; j < n_kv; ++j) {
+      c128 *vj = B + j * V12, *w = B + (j + 1) * V12;
+      launch_wilson<double>(c->gcan, U, vj, tmp, nullptr, m0, z, 1, W_QSHIFT, c->st, clov_can(c));
+      launch_wilson<double>(c->gcan, U, tmp, w, nullptr, m0, z, 1, W_QSHIFT, c->st, clov_can(c));
+      ++out.matvecs;
+      std::vector<cd> h1 = gram(c, j + 1, B, V12, 1, w, V12, V12);
+      combine(c, j + 1, B, V12, 1, h1, -1.0, w, V12, V12, true);
+      std::vector<cd> h2 = gram(c, j + 1, B, V12, 1, w, V12, V12);
+      combine(c, j + 1, B, V12, 1, h2, -1.0, w, V12, V12, true);
+      for (int i = 0; i <= j; ++i) {
+        const cd t = h1[i] + h2[i];
+        at(T, n_kv, i, j) = (i == j) ? cd(t.real(), 0.0) : t;
+        at(T, n_kv, j, i) = (i == j) ? cd(t.real(), 0.0) : std::conj(t);
+      }
+      beta = norms<double>(c, w, V12, 1)[0];
+      if (!(beta > 0)) fail(LQ_ERR_NUMERIC, "lanczos_lowmodes: the Krylov space became invariant");
+      if (j + 1 < n_kv) {
+        at(T, n_kv, j + 1, j) = at(T, n_kv, j, j + 1) = cd(beta);
+        scale<double>(c, {cd(1.0 / beta)}, w, V12, w, V12, V12, 1, false);
+      }
+    }
+    // Rayleigh-Ritz with Q^2 on the basis
+    std::vector<cd> A = T;
+    herm_eigh(n_kv, A, Z);
+    theta.resize(n_kv);
+    ord.resize(n_kv);
+    for (int i = 0; i < n_kv; ++i) { theta[i] = A[(size_t)i * n_kv + i].real(); ord[i] = i; }
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return theta[a] < theta[b]; });
+    // A B_i = sum_l B_l T_li (+ beta b_nkv for the last column): the residual of
+    // Ritz pair i is beta |z_i[n_kv - 1]|; converged when it is below tol 2|lambda|
+    int nconv = 0;
+    for (int r = 0; r < n_want; ++r) {
+      const int i = ord[r];
+      const double res = beta * std::abs(Z[(size_t)(n_kv - 1) * n_kv + i]);
+      const double lam_abs = std::sqrt(std::max(theta[i], 0.0));
+      if (res <= tol * 2.0 * lam_abs) ++nconv;
+      else break;
+    }
+    if (verbose())
+      std::fprintf(stderr, "[lqmg] lanczos cycle %d: %d of %d converged, %lld Q^2 products\n", out.restarts, nconv,
+                   n_want, out.matvecs);
+    if (nconv >= n_want) { out.converged = true; break; }
+    if (out.restarts >= max_restarts) break;
+    // thick restart: the kk lowest Ritz vectors, then the last Lanczos vector
+    const int kk = std::min(n_kv - 8, std::max(n_want + (n_kv - n_want) / 2, n_want + 1));
+    for (int i0 = 0; i0 < kk; i0 += kMaxRhs) {
+      const int nk = std::min(kMaxRhs, kk - i0);
+      std::vector<cd> Y((size_t)n_kv * nk);
+      for (int l = 0; l < n_kv; ++l)
+        for (int q = 0; q < nk; ++q) Y[(size_t)l * nk + q] = Z[(size_t)l * n_kv + ord[i0 + q]];
+      combine(c, n_kv, B, V12, nk, Y, 1.0, B2 + (long long)i0 * V12, V12, V12, false);
+    }
+    scale<double>(c, {cd(1.0 / beta)}, B + (long long)n_kv * V12, V12, B2 + (long long)kk * V12, V12, V12, 1,
+                  false);
+    std::fill(T.begin(), T.end(), cd(0));
+    for (int i = 0; i < kk; ++i) {
+      at(T, n_kv, i, i) = cd(theta[ord[i]]);
+      const cd a = beta * Z[(size_t)(n_kv - 1) * n_kv + ord[i]];
+      at(T, n_kv, kk, i) = a;
+      at(T, n_kv, i, kk) = std::conj(a);
+    }
+    std::swap(B, B2);
+    std::swap(c->lz_basis[0].p, c->lz_basis[1].p);
+    std::swap(c->lz_basis[0].n, c->lz_basis[1].n);
+    k = kk;
+    ++out.restarts;
+  }
+  // Ritz vectors of the n_want lowest, then Rayleigh-Ritz with Q on them
+  const int nw = n_want;
+  for (int i0 = 0; i0 < nw; i0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, nw - i0);
+    std::vector<cd> Y((size_t)n_kv * nk);
+    for (int l = 0; l < n_kv; ++l)
+      for (int q = 0; q < nk; ++q) Y[(size_t)l * nk + q] = Z[(size_t)l * n_kv + ord[i0 + q]];
+    combine(c, n_kv, B, V12, nk, Y, 1.0, B2 + (long long)i0 * V12, V12, V12, false);
+  }
+  std::vector<cd> G((size_t)nw * nw);
+  for (int j0 = 0; j0 < nw; j0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, nw - j0);
+    launch_wilson<double>(c->gcan, U, B2 + (long long)j0 * V12, tmp, nullptr, m0, z, nk, W_QSHIFT, c->st,
+                          clov_can(c));
+    auto g = gram(c, nw, B2, V12, nk, tmp, V12, V12);
+    for (int i = 0; i < nw; ++i)
+      for (int q = 0; q < nk; ++q) G[(size_t)i * nw + j0 + q] = g[(size_t)i * nk + q];
+  }
+  for (int i = 0; i < nw; ++i)
+    for (int j = i; j < nw; ++j) {
+      const cd h = 0.5 * (G[(size_t)i * nw + j] + std::conj(G[(size_t)j * nw + i]));
+      G[(size_t)i * nw + j] = h;
+      G[(size_t)j * nw + i] = std::conj(h);
+    }
+  std::vector<cd> Zq;
+  herm_eigh(nw, G, Zq);
+  std::vector<double> mu(nw);
+  std::vector<int> oq(nw);
+  for (int i = 0; i < nw; ++i) { mu[i] = G[(size_t)i * nw + i].real(); oq[i] = i; }
+  std::sort(oq.begin(), oq.end(), [&](int a, int b) { return std::fabs(mu[a]) < std::fabs(mu[b]); });
+  for (int i0 = 0; i0 < n_eig; i0 += kMaxRhs) {
+    const int nk = std::min(kMaxRhs, n_eig - i0);
+    std::vector<cd> Y((size_t)nw * nk);
+    for (int l = 0; l < nw; ++l)
+      for (int q = 0; q < nk; ++q) Y[(size_t)l * nk + q] = Zq[(size_t)l * nw + oq[i0 + q]];
+    c128 *X = Vout + (long long)i0 * V12;
+    combine(c, nw, B2, V12, nk, Y, 1.0, X, V12, V12, false);
+    // residuals ||Q x - lambda x||
+    launch_wilson<double>(c->gcan, U, X, tmp, nullptr, m0, z, nk, W_QSHIFT, c->st, clov_can(c));
+    std::vector<cd> a(nk);
+    for (int q = 0; q < nk; ++q) {
+      lam[i0 + q] = mu[oq[i0 + q]];
+      a[q] = cd(-lam[i0 + q]);
+    }
+    scale<double>(c, a, X, V12, tmp, V12, V12, nk, true);
+    auto r = norms<double>(c, tmp, V12, nk);
+    for (int q = 0; q < nk; ++q) resid[i0 + q] = r[q];
+  }
+  return out;
+}
 }  // namespace
 
 extern "C" {
@@ -2135,7 +2330,8 @@ int lma_high(lq_ctx *c, const lq_c128 *U, double m0, int n, const lq_c128 *V, co
           for (int i = 0; i < L.n; ++i) Y[(size_t)i * nk + k] = col[i];
         }
         combine(c, L.n, c->lma_V.p, V12, nk, Y, 1.0, X, V12, V12, false);                 // X = V y
-        launch_wilson<double>(c->gcan, (const c128 *)U, X, xb, R, m0, shifts_of(nullptr, 0), nk, W_RESID, c->st);
+        launch_wilson<double>(c->gcan, (const c128 *)U, X, xb, R, m0, shifts_of(nullptr, 0), nk, W_RESID, c->st,
+                              clov_can(c));
         copy<double>(c, R, xb, (size_t)nk * V12);                                        // R = eta - Q V y
       }
       // s = Q^{-1} R~ eta by the multigrid-preconditioned FGMRES (sigma = 0)
@@ -2156,6 +2352,26 @@ int lma_high(lq_ctx *c, const lq_c128 *U, double m0, int n, const lq_c128 *V, co
           loop_high[((size_t)(k0 + k) * T + t) * 2 + 1] = h[t].imag();
         }
       }
+    }
+    return LQ_OK;
+  });
+}
+
+int lanczos_lowmodes(lq_ctx *c, const lq_c128 *U, double m0, int n_eig, int n_guard, int n_kv, double tol,
+                     int max_restarts, const lq_c128 *v0, double *lambda, lq_c128 *V, double *resid, int *info) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !v0 || !lambda || !V || !resid || n_eig < 1 || n_guard < 0 || !(tol > 0) || max_restarts < 0)
+      fail(LQ_ERR_ARG, "lanczos_lowmodes: bad arguments");
+    const int n_want = n_eig + n_guard;
+    if (n_kv > 191 || n_kv < n_want + 16)
+      fail(LQ_ERR_ARG, "lanczos_lowmodes: need n_eig + n_guard + 16 <= n_kv <= 191");
+    LanczosOut o = lanczos_q2(c, (const c128 *)U, m0, n_eig, n_want, n_kv, tol, max_restarts, (const c128 *)v0,
+                              lambda, (c128 *)V, resid);
+    if (info) {
+      info[0] = o.restarts;
+      info[1] = (int)std::min<long long>(o.matvecs, 0x7fffffff);
+      info[2] = o.converged ? 1 : 0;
     }
     return LQ_OK;
   });

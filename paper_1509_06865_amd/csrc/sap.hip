@@ -20,14 +20,14 @@ template <typename T> __device__ inline T wsumT(T v) {
   return v;
 }
 
-template <typename T>
 // Registers capped for four waves per SIMD (a few values spill; measured
 // faster than three waves without spills: 0.179 against 0.186 ms per 16-field
-// pass on 16^4)
+// pass on 16^4).  With CLOV the site term carries the clover term.
+template <typename T, bool CLOV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sap_colour(Geom g, const cplx<T> *__restrict__ U,
                                                     const cplx<T> *__restrict__ rin, cplx<T> *__restrict__ zio,
                                                     const int *__restrict__ blocks, T m0, Shifts sig, int n_mr,
-                                                    int nrhs) {
+                                                    int nrhs, const cplx<T> *__restrict__ C) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T> *lds = reinterpret_cast<cplx<T> *>(smem_raw);          // [12][bvol]
   __shared__ T red[4][3];                        // per-wave partial sums (<= 4 waves)
@@ -109,6 +109,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       for (int i = 0; i < 12; ++i) q[i] = z[(long long)i * g.V + sb];
       hop(mu, false, q, U, g.V, sb, sgb, acc);
     }
+    if constexpr (CLOV) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) q[i] = z[(long long)i * g.V + s];
+      clover_add(C, g.V, s, q, (T)-2, acc);         // -1/2 acc then adds C z
+    }
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
       const cplx<T> zi = z[(long long)i * g.V + s];
@@ -155,6 +160,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           hop(mu, false, q, U, g.V, s - slm, (T)1, acc);
         }
       }
+      if constexpr (CLOV) clover_add(C, g.V, s, rho, (T)-2, acc);
 #pragma unroll
       for (int i = 0; i < 12; ++i) {
         const T g5 = (i < 6) ? (T)1 : (T)-1;
@@ -190,21 +196,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 template <typename T>
 void launch_sap_colour(const Geom &g, const cplx<T> *U, const cplx<T> *r, cplx<T> *z, const int *blocks,
-                       int nblocks, double m0, const Shifts &sig, int nrhs, int n_mr, hipStream_t st) {
+                       int nblocks, double m0, const Shifts &sig, int nrhs, int n_mr, hipStream_t st,
+                       const cplx<T> *C) {
   if (nblocks <= 0 || nrhs <= 0) return;
   const int threads = ((g.bvol + 63) / 64) * 64;
-  // algorithmic bytes: the colour's links once; per field r, z of the colour's
-  // sites and of the other colour's (the blocks' halo), z out
-  KTimerScope kt(KT_SAP, (double)nblocks * g.bvol * (36.0 + 48.0 * nrhs) * sizeof(cplx<T>));
+  // algorithmic bytes: the colour's links (and clover blocks) once; per field
+  // r, z of the colour's sites and of the other colour's (the blocks' halo), z out
+  KTimerScope kt(KT_SAP, (double)nblocks * g.bvol * (36.0 + (C ? 42.0 : 0.0) + 48.0 * nrhs) * sizeof(cplx<T>));
   const size_t lds = (size_t)12 * g.bvol * sizeof(cplx<T>);
-  LQ_LAUNCH(kt, (k_sap_colour<T>), dim3(nblocks * nrhs), dim3(threads), lds, st, g, U, r, z, blocks, (T)m0,
-                     sig, n_mr, nrhs);
+  if (C)
+    LQ_LAUNCH(kt, (k_sap_colour<T, true>), dim3(nblocks * nrhs), dim3(threads), lds, st, g, U, r, z, blocks,
+              (T)m0, sig, n_mr, nrhs, C);
+  else
+    LQ_LAUNCH(kt, (k_sap_colour<T, false>), dim3(nblocks * nrhs), dim3(threads), lds, st, g, U, r, z, blocks,
+              (T)m0, sig, n_mr, nrhs, C);
   LQ_HIP(hipGetLastError());
 }
 
 template void launch_sap_colour<float>(const Geom &, const c64 *, const c64 *, c64 *, const int *, int, double,
-                                       const Shifts &, int, int, hipStream_t);
+                                       const Shifts &, int, int, hipStream_t, const c64 *);
 template void launch_sap_colour<double>(const Geom &, const c128 *, const c128 *, c128 *, const int *, int,
-                                        double, const Shifts &, int, int, hipStream_t);
+                                        double, const Shifts &, int, int, hipStream_t, const c128 *);
 
 }  // namespace lq

@@ -10,10 +10,12 @@ namespace {
 
 // One thread per site and R right-hand sides: each link is loaded once and
 // applied to the R fields, so the links are read once per group of R fields.
-template <typename T, int MODE, int R>
+// With CLOV the site term carries the clover term C(x) (lq_dslash.h).
+template <typename T, int MODE, int R, bool CLOV>
 __global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restrict__ U,
                                                 const cplx<T> *__restrict__ xin, cplx<T> *__restrict__ yout,
-                                                const cplx<T> *__restrict__ bin, T m0, Shifts sig, int nrhs) {
+                                                const cplx<T> *__restrict__ bin, T m0, Shifts sig, int nrhs,
+                                                const cplx<T> *__restrict__ C) {
   const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int k0 = blockIdx.y * R;
@@ -54,6 +56,7 @@ __global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restric
     if (r >= nr) break;
     const long long off = (k0 + r) * fs;
     load_spinor(x + r * fs, g.V, s, p);
+    if constexpr (CLOV) clover_add(C, g.V, s, p, (T)-2, acc[r]);     // -1/2 acc then adds C p
     const T sgm = (T)sig.s[k0 + r];
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
@@ -74,10 +77,10 @@ __global__ void __launch_bounds__(256) k_wilson(Geom g, const cplx<T> *__restric
 // is read once per column.  Consecutive threads take consecutive spatial
 // sites (coalesced); column chunks are renumbered per XCD like the other
 // stencil launches.
-template <typename T>
+template <typename T, bool CLOV>
 __global__ void __launch_bounds__(256) k_wilson_tcol(Geom g, const cplx<T> *__restrict__ U,
                                                      const cplx<T> *__restrict__ x, cplx<T> *__restrict__ y, T m0,
-                                                     int TC) {
+                                                     int TC, const cplx<T> *__restrict__ C) {
   const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2], L3 = g.L[3];
   const int S3 = L0 * L1 * L2;
   const int nchunk = (L3 + TC - 1) / TC;
@@ -136,6 +139,7 @@ __global__ void __launch_bounds__(256) k_wilson_tcol(Geom g, const cplx<T> *__re
     project(3, (T)1, xc, h);
     link_mul(m, h, ub, true);
     ubsign = (T)1;
+    if constexpr (CLOV) clover_add(C, V, n, xc, (T)-2, acc);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
       cplx<T> d = diag * xc[i] - (T)0.5 * acc[i];
@@ -147,10 +151,11 @@ __global__ void __launch_bounds__(256) k_wilson_tcol(Geom g, const cplx<T> *__re
 }
 
 // Parts of Q for the Galerkin product, per column field j.
-template <typename T>
+template <typename T, bool CLOV>
 __global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__restrict__ U,
                                                       const cplx<T> *__restrict__ xin, long long xstride,
-                                                      cplx<T> *__restrict__ parts, T m0, const int *half_dev) {
+                                                      cplx<T> *__restrict__ parts, T m0, const int *half_dev,
+                                                      const cplx<T> *__restrict__ C) {
   const int s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const int j = blockIdx.y;
@@ -170,6 +175,7 @@ __global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__r
   ld(s, p);
 #pragma unroll
   for (int i = 0; i < 12; ++i) self[i] = ((T)4 + m0) * p[i];
+  if constexpr (CLOV) clover_add(C, g.V, s, p, (T)1, self);         // keeps the gamma5 half
 #pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     float sg;
@@ -201,55 +207,70 @@ __global__ void __launch_bounds__(256) k_coarse_parts(Geom g, const cplx<T> *__r
   for (int i = 0; i < 12; ++i) out[(long long)i * g.V + s] = (i >= 6) ? -self[i] : self[i];
 }
 
-}  // namespace
-
 // fields per thread in the Wilson kernel: registers allow 2 in FP64, 4 in FP32
 template <typename T> constexpr int wilson_group() { return sizeof(T) == 4 ? 4 : 2; }
 
-template <typename T>
-void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y, const cplx<T> *b,
-                   double m0, const Shifts &sig, int nrhs, int mode, hipStream_t st) {
-  if (nrhs <= 0) return;
+template <typename T, bool CLOV>
+void wilson_launch(KTimerScope &kt, const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y,
+                   const cplx<T> *b, double m0, const Shifts &sig, int nrhs, int mode, hipStream_t st,
+                   const cplx<T> *C) {
   constexpr int R = wilson_group<T>();
-  // algorithmic bytes: links once, each field in and out (and b when forming residuals)
-  KTimerScope kt(KT_WILSON, (double)g.V * (36.0 + nrhs * (mode == W_RESID ? 36.0 : 24.0)) * sizeof(cplx<T>));
   constexpr int TC = 8;                        // timeslices per thread of the column kernel
   const long long cols = (long long)g.L[0] * g.L[1] * g.L[2] * ((g.L[3] + TC - 1) / TC);
   // the column kernel when its columns fill the GPU (>= 256 workgroups; 32^3 x 64: 1024)
   if (nrhs == 1 && mode == W_QSHIFT && g.nblk == 1 && sig.s[0] == 0.0 && g.L[3] >= 2 && cols >= 256 * 256) {
-    LQ_LAUNCH(kt, (k_wilson_tcol<T>), dim3(blocks_for(cols, 256)), dim3(256), 0, st, g, U, x, y, (T)m0, TC);
+    LQ_LAUNCH(kt, (k_wilson_tcol<T, CLOV>), dim3(blocks_for(cols, 256)), dim3(256), 0, st, g, U, x, y, (T)m0, TC,
+              C);
   } else if (nrhs == 1) {
     const dim3 grid(blocks_for(g.V, 256), 1);
     if (mode == W_QSHIFT)
-      LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, 1, CLOV>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs, C);
     else
-      LQ_LAUNCH(kt, (k_wilson<T, W_RESID, 1>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_RESID, 1, CLOV>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs, C);
   } else {
     const dim3 grid(blocks_for(g.V, 256), (nrhs + R - 1) / R);
     if (mode == W_QSHIFT)
-      LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_QSHIFT, R, CLOV>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs, C);
     else
-      LQ_LAUNCH(kt, (k_wilson<T, W_RESID, R>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs);
+      LQ_LAUNCH(kt, (k_wilson<T, W_RESID, R, CLOV>), grid, dim3(256), 0, st, g, U, x, y, b, (T)m0, sig, nrhs, C);
   }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_wilson(const Geom &g, const cplx<T> *U, const cplx<T> *x, cplx<T> *y, const cplx<T> *b,
+                   double m0, const Shifts &sig, int nrhs, int mode, hipStream_t st, const cplx<T> *C) {
+  if (nrhs <= 0) return;
+  // algorithmic bytes: links once, each field in and out (and b when forming
+  // residuals), the clover blocks once
+  KTimerScope kt(KT_WILSON, (double)g.V * (36.0 + (C ? 42.0 : 0.0) + nrhs * (mode == W_RESID ? 36.0 : 24.0)) *
+                                sizeof(cplx<T>));
+  if (C) wilson_launch<T, true>(kt, g, U, x, y, b, m0, sig, nrhs, mode, st, C);
+  else wilson_launch<T, false>(kt, g, U, x, y, b, m0, sig, nrhs, mode, st, C);
   LQ_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_coarse_parts(const Geom &g, const cplx<T> *U, const cplx<T> *x, const int *half_dev,
-                         int nf, long long xstride, cplx<T> *parts, double m0, hipStream_t st) {
+                         int nf, long long xstride, cplx<T> *parts, double m0, hipStream_t st, const cplx<T> *C) {
   dim3 grid(blocks_for(g.V, 256), nf);
-  hipLaunchKernelGGL((k_coarse_parts<T>), grid, dim3(256), 0, st, g, U, x, xstride, parts, (T)m0,
-                     half_dev);
+  if (C)
+    hipLaunchKernelGGL((k_coarse_parts<T, true>), grid, dim3(256), 0, st, g, U, x, xstride, parts, (T)m0,
+                       half_dev, C);
+  else
+    hipLaunchKernelGGL((k_coarse_parts<T, false>), grid, dim3(256), 0, st, g, U, x, xstride, parts, (T)m0,
+                       half_dev, C);
   LQ_HIP(hipGetLastError());
 }
 
 template void launch_wilson<float>(const Geom &, const c64 *, const c64 *, c64 *, const c64 *, double,
-                                   const Shifts &, int, int, hipStream_t);
+                                   const Shifts &, int, int, hipStream_t, const c64 *);
 template void launch_wilson<double>(const Geom &, const c128 *, const c128 *, c128 *, const c128 *, double,
-                                    const Shifts &, int, int, hipStream_t);
+                                    const Shifts &, int, int, hipStream_t, const c128 *);
 template void launch_coarse_parts<float>(const Geom &, const c64 *, const c64 *, const int *, int, long long,
-                                         c64 *, double, hipStream_t);
+                                         c64 *, double, hipStream_t, const c64 *);
 template void launch_coarse_parts<double>(const Geom &, const c128 *, const c128 *, const int *, int,
-                                          long long, c128 *, double, hipStream_t);
+                                          long long, c128 *, double, hipStream_t, const c128 *);
 
 }  // namespace lq

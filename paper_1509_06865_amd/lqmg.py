@@ -25,7 +25,8 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "mg_restrict", "mg_prolong", "mg_coarse_apply", "mg_smooth", "mg_cycle", "lq_inner_products",
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
             "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc", "mg_info2",
-            "mg_get_level2", "lma_low", "lma_high", "lq_timeslice_products"]
+            "mg_get_level2", "lma_low", "lma_high", "lq_timeslice_products", "lanczos_lowmodes",
+            "lq_clover"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -127,6 +128,8 @@ def load():
         "lma_low": (i, [vp, vp, d, i, vp, dp, dp, d, dp, dp, ip]),
         "lma_high": (i, [vp, vp, d, i, vp, dp, dp, d, i, vp, d, dp]),
         "lq_timeslice_products": (i, [vp, i, vp, i, vp, vp]),
+        "lanczos_lowmodes": (i, [vp, vp, d, i, i, i, d, i, vp, dp, vp, dp, ip]),
+        "lq_clover": (i, [vp, vp, d]),
         "mg_get_level2": (i, [vp, vp, vp]),
         "mg_solve_shifted": (i, [vp, i, dp, vp, vp, d, C.POINTER(_SolveStats)]),
         "rqi_lowmodes": (i, [vp, i, d, dp, vp, dp, vp, i, C.POINTER(_RQIStats)]),
@@ -219,6 +222,14 @@ class Context:
         return rc
 
     # -- Q ----------------------------------------------------------------------
+    def clover(self, U: torch.Tensor | None, csw: float):
+        """Set the clover term built from U (device [4, 9, V] complex128) with
+        coefficient csw for every later operator application; csw = 0 removes
+        it.  Drops the hierarchy (call mg_setup afterwards)."""
+        if U is not None:
+            _need(U, "U", (4, 9, self.V), torch.complex128)
+        self._check(self.lib.lq_clover(self.h, _ptr(U) if U is not None else None, float(csw)))
+
     def q_apply(self, U: torch.Tensor, m0: float, x: torch.Tensor, out: torch.Tensor | None = None):
         n = x.shape[0] if x.dim() == 3 else 1
         y = torch.empty_like(x) if out is None else out
@@ -493,6 +504,23 @@ class Context:
         self._check(self.lib.lq_timeslice_products(self.h, nb, _ptr(E), nw, _ptr(W), C.c_void_p(out.ctypes.data)))
         return out
 
+    # -- restarted Krylov eigensolver (the comparison of sec. 2.2) -------------------
+    def lanczos_lowmodes(self, U, m0, n_eig, v0, tol=1e-10, n_kv=100, n_guard=4, max_restarts=1000):
+        """The n_eig lowest-|lambda| eigenpairs of Q by restarted Lanczos on Q^2 (no multigrid).
+        v0: device start vector [12, V] complex128.  Returns (lambda, V [n_eig, 12, V] device,
+        residuals, {"restarts", "q2_products", "converged"})."""
+        import numpy as np
+        _need(v0, "v0", (12, self.V), torch.complex128)
+        lam = np.zeros(n_eig)
+        res = np.zeros(n_eig)
+        Vout = torch.empty((n_eig, 12, self.V), dtype=torch.complex128, device=v0.device)
+        info = (C.c_int * 3)()
+        self._check(self.lib.lanczos_lowmodes(self.h, _ptr(U), float(m0), int(n_eig), int(n_guard), int(n_kv),
+                                              float(tol), int(max_restarts), _ptr(v0),
+                                              lam.ctypes.data_as(C.POINTER(C.c_double)), _ptr(Vout),
+                                              res.ctypes.data_as(C.POINTER(C.c_double)), info))
+        return lam, Vout, res, {"restarts": info[0], "q2_products": info[1], "converged": bool(info[2])}
+
     def cycle(self, sigma, r):
         z = torch.empty_like(r)
         self._check(self.lib.mg_cycle(self.h, r.shape[0], _dbl(sigma), _ptr(r), _ptr(z)))
@@ -516,7 +544,8 @@ def kernel_timer_read():
 
 
 def coarse_variant(v: int) -> None:
-    """Force coarse-apply kernel v (0..6; 6 = matrix cores) for every shape, or -1 for the tuned choice."""
+    """Force coarse-apply kernel v (0..7; 6 = matrix cores in FP32, 7 = matrix cores on bfloat16 operands) for
+    every shape, or -1 for the tuned choice."""
     rc = load().lq_coarse_variant(int(v))
     if rc != 0:
         raise LQError(rc, f"lq_coarse_variant({v}) failed")

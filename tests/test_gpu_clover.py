@@ -1,0 +1,194 @@
+"""The clover term on the device (lq_clover) against the oracle's clover-
+improved operator (oracle/clover.py, pinned in test_oracle_clover.py): Q
+itself in FP64 and FP32, every multigrid piece that applies D (coarse
+operator, SAP, cycle) element by element, and the lowest eigenpairs of RQI
+and of the Krylov solver against the dense spectrum of the oracle's Q.
+Tolerances as in test_gpu_parity."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import lqsynth
+from oracle import mg as M
+from oracle.dirac import Lattice, WilsonOp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+CSW = 1.7
+
+
+def dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), -1), ((6, 4, 2, 8), 1), ((8, 4, 4, 2), -1)])
+def test_q_apply_with_clover_matches_oracle(dims, bc):
+    from paper_1509_06865_amd import Context
+    print(f"[clover q_apply] {dims} bc {bc}", flush=True)
+    U = lqsynth.gauge_field(dims, 0.5, 21)
+    x = lqsynth.gaussian_spinors(3, dims, 22)
+    c = Context(dims, bc)
+    Ud = dev(U)
+    c.clover(Ud, CSW)
+    y = host(c.q_apply(Ud, -0.1, dev(x)))
+    op = WilsonOp(U, -0.1, Lattice(dims, bc), csw=CSW)
+    ref = op.Q(x)
+    assert relmax(y, ref) < 1e-13
+    # FP32 links and fields
+    y32 = host(c.q_apply(dev(U, torch.complex64), -0.1, dev(x, torch.complex64)))
+    assert relmax(y32, ref) < 2e-6
+    # and the term is really there
+    assert relmax(ref, WilsonOp(U, -0.1, Lattice(dims, bc)).Q(x)) > 1e-3
+    # c_sw = 0 returns to the plain operator
+    c.clover(None, 0.0)
+    assert relmax(host(c.q_apply(Ud, -0.1, dev(x))), WilsonOp(U, -0.1, Lattice(dims, bc)).Q(x)) < 1e-13
+
+
+def test_q_apply_with_clover_column_kernel():
+    # a lattice large enough for the timeslice-column kernel (one field, canonical)
+    from paper_1509_06865_amd import Context
+    dims = (16, 16, 16, 8)
+    print(f"[clover q_apply column kernel] {dims}", flush=True)
+    U = lqsynth.gauge_field(dims, 0.4, 23)
+    x = lqsynth.gaussian_spinors(1, dims, 24)
+    c = Context(dims, -1)
+    Ud = dev(U)
+    c.clover(Ud, CSW)
+    y = host(c.q_apply(Ud, 0.05, dev(x[0])))
+    lat = Lattice(dims, -1)
+    from oracle.clover import apply_clover, clover_matrix
+    from oracle.dirac import apply_Q, gamma5
+    ref = apply_Q(U, 0.05, x[0], lat) + gamma5(apply_clover(clover_matrix(U, lat, CSW), x[0]))
+    assert relmax(y, ref) < 1e-13
+
+
+DIMS, AGG = (8, 8, 4, 4), (4, 4, 2, 2)
+
+
+@pytest.fixture(scope="module", params=[0, 1], ids=["fp64", "mixed"])
+def hier_clover(request):
+    from paper_1509_06865_amd import Context, MGParams
+    nv, m0 = 8, -0.25
+    print(f"[clover hierarchy] {DIMS}, aggregates {AGG}, Nv={nv}, precision {request.param}", flush=True)
+    U = lqsynth.gauge_field(DIMS, 0.4, 31)
+    lat = Lattice(DIMS, -1)
+    op = WilsonOp(U, m0, lat, csw=CSW)
+    ag = M.Aggregation(lat, AGG)
+    tv0 = lqsynth.gaussian_spinors(nv, DIMS, 32)
+    prm = MGParams(precision=request.param, n_init=0, n_setup=0, coarse_m=160, coarse_tol=1e-10,
+                   coarse_restarts=3, post=2, sap_mr=4)
+    c = Context(DIMS, -1)
+    Ud = dev(U)
+    c.clover(Ud, CSW)
+    c.mg_setup(Ud, m0, AGG, dev(tv0), prm)
+    P = M.build_P(M.orthonormalise(tv0), ag)
+    Qc = M.coarse_operator(op, ag, P)
+    return dict(c=c, U=U, op=op, ag=ag, P=P, Qc=Qc, m0=m0, prec=request.param, nv=nv)
+
+
+def _tol(h, fp64, fp32):
+    return fp64 if h["prec"] == 0 else fp32
+
+
+def test_clover_coarse_operator_matches(hier_clover):
+    h = hier_clover
+    assert relmax(host(h["c"].get_interp()), h["P"]) < 1e-12
+    assert relmax(host(h["c"].get_coarse()), h["Qc"][:, :5]) < _tol(h, 1e-12, 3e-6)
+
+
+def test_clover_sap_matches(hier_clover):
+    h = hier_clover
+    r = lqsynth.gaussian_spinors(3, DIMS, 33)
+    sig = [0.0, 0.05, -0.11]
+    z = host(h["c"].smooth(sig, dev(r), 2))
+    ref = np.stack([M.sap(h["op"], h["ag"], sig[k], r[k], 2, 4) for k in range(3)])
+    assert relmax(z, ref) < _tol(h, 1e-11, 5e-5)
+
+
+def test_clover_cycle_matches(hier_clover):
+    h = hier_clover
+    mg = M.TwoLevel(h["op"], AGG, M.MGParams(pre=0, post=2, n_mr=4, coarse_m=160, coarse_tol=1e-10,
+                                             coarse_restarts=3))
+    mg.P, mg.Qc = h["P"], h["Qc"]
+    r = lqsynth.gaussian_spinors(2, DIMS, 34)
+    sig = [0.0, 0.03]
+    z = host(h["c"].cycle(sig, dev(r)))
+    ref = np.stack([mg.cycle(sig[k], r[k]) for k in range(2)])
+    assert relmax(z, ref) < _tol(h, 1e-8, 5e-5)
+
+
+def _dense_lowest(U, m0, dims, bc, n):
+    op = WilsonOp(U, m0, Lattice(dims, bc), csw=CSW)
+    N = 12 * int(np.prod(dims))
+    E = np.eye(N, dtype=np.complex128).reshape(N, 12, -1)
+    ev = np.linalg.eigvalsh(op.Q(E).reshape(N, N).T)
+    return ev[np.argsort(np.abs(ev), kind="stable")][:n], op
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_rqi_with_clover_lowest_eight_match_dense(prec):
+    from paper_1509_06865_amd import Context, MGParams
+    cfg = json.load(open(os.path.join(GOLDEN, "m0.json")))["tiny_antiperiodic"]
+    dims, bc, m0 = tuple(cfg["dims"]), cfg["t_bc"], cfg["m0"]
+    print(f"[clover rqi] {dims}, 8 lowest, precision {prec}", flush=True)
+    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
+    ref, op = _dense_lowest(U, m0, dims, bc, 8)
+    c = Context(dims, bc)
+    Ud = dev(U)
+    c.clover(Ud, CSW)
+    c.mg_setup(Ud, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(8, dims, 35)),
+               MGParams(precision=prec, coarse_m=128, coarse_tol=1e-8, coarse_restarts=2, n_setup=4, rqi_block=4,
+                        rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1))
+    # 8 pairs + 4 guard vectors: 4 start vectors beyond the 8 of the setup
+    lam, V, res, info = c.rqi_lowmodes(8, 1e-10, V0=dev(lqsynth.gaussian_spinors(4, dims, 37)))
+    assert info["converged"], info
+    lam = np.asarray(lam)
+    order = np.lexsort((lam, np.abs(lam)))
+    lam = lam[order]
+    assert np.all(np.abs(lam - ref) <= 1e-10 * np.abs(ref)), (lam, ref)
+    Vh = host(V)[order]
+    Qv = op.Q(Vh)
+    assert max(np.linalg.norm(Qv[i] - lam[i] * Vh[i]) for i in range(8)) <= 2e-10
+
+
+def test_lanczos_with_clover_lowest_eight_match_dense():
+    from paper_1509_06865_amd import Context
+    cfg = json.load(open(os.path.join(GOLDEN, "m0.json")))["tiny_periodic"]
+    dims, bc, m0 = tuple(cfg["dims"]), cfg["t_bc"], cfg["m0"]
+    print(f"[clover lanczos] {dims}, 8 lowest", flush=True)
+    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
+    ref, _ = _dense_lowest(U, m0, dims, bc, 8)
+    c = Context(dims, bc)
+    Ud = dev(U)
+    c.clover(Ud, CSW)
+    lam, V, res, info = c.lanczos_lowmodes(Ud, m0, 8, dev(lqsynth.gaussian_spinors(1, dims, 36)[0]), tol=1e-10,
+                                           n_kv=40, n_guard=4)
+    assert info["converged"], info
+    lam = np.asarray(lam)
+    lam = lam[np.lexsort((lam, np.abs(lam)))]
+    assert np.all(np.abs(lam - ref) <= 1e-10 * np.abs(ref)), (lam, ref)
+
+
+def test_clover_drops_the_hierarchy():
+    from paper_1509_06865_amd import Context, LQError, MGParams
+    dims = (4, 4, 4, 4)
+    U = dev(lqsynth.gauge_field(dims, 0.4, 41))
+    c = Context(dims, -1)
+    c.mg_setup(U, -0.1, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(4, dims, 42)), MGParams(n_setup=0))
+    c.clover(U, CSW)
+    with pytest.raises(LQError):
+        c.mg_solve_shifted([0.0], dev(lqsynth.gaussian_spinors(1, dims, 43)), 1e-6)
+    with pytest.raises(LQError):
+        c.clover(None, 1.0)                   # links needed for c_sw != 0
