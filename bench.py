@@ -241,7 +241,8 @@ KCLASS = {"wilson": (0, "Wilson stencil k_wilson (links once + fields in/out)"),
 def coarse_variants(args):
     """Time each coarse-apply kernel (0: one wave per (site, field); 1-3: LDS-staged
     blocks for 4, 8, 16 fields per pass; 4, 5: as 1, 2 per (site, chunk of
-    fields); 6: matrix cores) with the FP32 coarse operator and with its bfloat16 copy, on the
+    fields); 6: matrix cores in FP32; 7: matrix cores on bfloat16 operands, bfloat16
+    storage only) with the FP32 coarse operator and with its bfloat16 copy, on the
     coarse grid of a 16^3 x 32 lattice with 2^4 aggregates and Nv = 24 (8192
     coarse sites, 48 x 48 blocks), 16 fields, through the library's kernel timer.
     Prints one JSON line per (storage, kernel)."""
@@ -262,7 +263,7 @@ def coarse_variants(args):
     for bf16 in (0, 1):
         ctx = Context(dims, 1)
         ctx.mg_setup(U, -0.15, agg, tv0, MGParams(precision=1, n_setup=0, n_init=1, coarse_bf16=bf16))
-        for v in range(7):
+        for v in range(8 if bf16 else 7):
             coarse_variant(v)
             ctx.coarse_apply(sig, x)
             torch.cuda.synchronize()
@@ -480,6 +481,61 @@ def lma_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def lanczos_mode(args):
+    """The Krylov comparison of sec. 2.2 on the 16^4 benchmark field: the
+    n_eig lowest eigenpairs of Q at 1e-10 by restarted Lanczos on Q^2 (no
+    multigrid; a basis of n_kv vectors restarted from the lowest Ritz vectors)
+    and by RQI with the multigrid (the benchmark's parameters), for each n_eig
+    of --lanczos-neig, on the same GPU.  The eigenvalues of the two must agree.
+    Prints one JSON line."""
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import Context, MGParams
+    gold = load_golden("medium")
+    dims, m0 = tuple(gold["dims"]), gold["m0"]
+    U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
+    ctx = Context(dims, gold["t_bc"])
+    wl = WORKLOADS["medium"]
+    out = {"workload": f"16^4 eps={gold['eps']} m0={m0}, tol 1e-10", "runs": []}
+    for n_eig in [int(x) for x in args.lanczos_neig.split(",")]:
+        n_kv = min(191, max(100, 2 * n_eig + 40))
+        v0 = device_gaussian(1, dims, gold["field_seed"] + 7, torch)[0]
+        torch.cuda.synchronize()
+        a = time.time()
+        lam_l, V_l, res_l, info_l = ctx.lanczos_lowmodes(U, m0, n_eig, v0, tol=1e-10, n_kv=n_kv, n_guard=4,
+                                                         max_restarts=args.lanczos_max_restarts)
+        torch.cuda.synchronize()
+        t_l = time.time() - a
+        del V_l
+        log(f"lanczos n_eig {n_eig} n_kv {n_kv}: {t_l:.2f} s, {info_l}")
+        # the guard band reaches past the momentum shell the n_eig-th mode lies in
+        # (16^4: 12 + 96 modes), as for the benchmark's 50 pairs
+        guard = max(wl["guard"], 120 - n_eig)
+        p = MGParams(precision=1, rqi_guard=guard, rayleigh_ritz=1, **wl["params"])
+        tv0 = device_gaussian(wl["nv"], dims, gold["field_seed"] + 1, torch)
+        torch.cuda.synchronize()
+        a = time.time()
+        ctx.mg_setup(U, m0, wl["agg"], tv0, p)
+        V0 = device_gaussian(n_eig + guard - wl["nv"], dims, gold["field_seed"] + 2, torch) \
+            if n_eig + guard > wl["nv"] else None
+        lam_r, V_r, res_r, info_r = ctx.rqi_lowmodes(n_eig, 1e-10, V0=V0)
+        torch.cuda.synchronize()
+        t_r = time.time() - a
+        del V_r, V0, tv0
+        log(f"rqi n_eig {n_eig}: {t_r:.2f} s, sweeps {info_r['sweeps']}")
+        lr = np.sort(np.asarray(lam_r))
+        ll = np.sort(np.asarray(lam_l))
+        out["runs"].append({"n_eig": n_eig, "n_kv": n_kv,
+                            "lanczos": {"s": round(t_l, 3), "q2_products": info_l["q2_products"],
+                                        "restarts": info_l["restarts"], "converged": info_l["converged"],
+                                        "max_residual": float(np.max(res_l))},
+                            "rqi_mg": {"s": round(t_r, 3), "sweeps": info_r["sweeps"], "solves": info_r["solves"],
+                                       "converged": info_r["converged"], "max_residual": float(np.max(res_r))},
+                            "speedup": round(t_l / t_r, 2),
+                            "max_rel_eigenvalue_diff": float(np.max(np.abs(lr - ll) / np.abs(lr)))})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,10 +564,14 @@ def main():
     ap.add_argument("--lma", action="store_true", help="approximate low-mode averaging on the 16^4 field")
     ap.add_argument("--lma-modes", type=int, default=20)
     ap.add_argument("--lma-noise", type=int, default=32)
+    ap.add_argument("--lanczos", action="store_true",
+                    help="restarted Lanczos on Q^2 against RQI with the multigrid on the 16^4 field (sec. 2.2)")
+    ap.add_argument("--lanczos-neig", default="20,50")
+    ap.add_argument("--lanczos-max-restarts", type=int, default=2000)
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the roofline kernel class and a reference copy (for counter passes)")
     ap.add_argument("--coarse-variants", action="store_true",
-                    help="time the six coarse-apply kernels with FP32 and bfloat16 storage (8192 coarse sites)")
+                    help="time the coarse-apply kernels with FP32 and bfloat16 storage (8192 coarse sites)")
     ap.add_argument("--roofline-class", default=DEFAULT_CLASS, choices=sorted(KCLASS) + ["all"],
                     help="kernel class timed live for the roofline object (default: the step's dominant one)")
     args = ap.parse_args()
@@ -527,6 +587,9 @@ def main():
         return
     if args.lma:
         lma_mode(args)
+        return
+    if args.lanczos:
+        lanczos_mode(args)
         return
     if args.kernel_only:
         kernel_only(args)
