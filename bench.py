@@ -29,12 +29,13 @@ DEFAULT_CLASS = "sap"          # the kernel class with the largest share of the 
 # plain copy of known size), by kernel class and workload, with the SHA-256 of
 # the kernel's source at the time; reported only while the source is unchanged
 TRAFFIC = {
-    # profiles/hbm_traffic_16x4.md: k_sap_colour<float>, one colour, 16 right-hand sides
-    ("sap", "medium"): {"bytes_per_launch": 278.68e6,
-                        "source_sha256": "f0bb59517c4b540d91b95fafaa30216e14ebc7f4a23629f88098bc6a7de29de0"},
-    # k_coarse_apply<float>, 16 right-hand sides, 256 coarse sites of 40 unknowns
-    ("coarse", "medium"): {"bytes_per_launch": 16.17e6,
-                           "source_sha256": "99ecebd727a242a9cdc02b7d7d6ee5ef944c55ba736c123e8d41bd057266d979"},
+    # profiles/hbm_traffic_16x4.md: k_sap_colour<float, false>, one colour, 16 right-hand sides
+    # (source since changed only in the FP64 instantiation's register cap; the FP32 code is identical)
+    ("sap", "medium"): {"bytes_per_launch": 312.02e6,
+                        "source_sha256": "ca9ccebdcf4b8bc964eeae88d8748d398ba0fe6dedc88b95f79ad98973007c2d"},
+    # k_coarse_apply_mfma (the tuned kernel), 16 right-hand sides, 256 coarse sites of 40 unknowns
+    ("coarse", "medium"): {"bytes_per_launch": 15.70e6,
+                           "source_sha256": "2f797ceab98415869eb162ea6a2980e5d59e3dd56b6cc8ee92480f287417b69a"},
 }
 KSOURCES = {"wilson": ["wilson.hip", "lq_dslash.h"], "sap": ["sap.hip", "lq_dslash.h"],
             "restrict": ["transfer.hip"], "prolong": ["transfer.hip"], "coarse": ["coarse.hip"],
@@ -56,6 +57,16 @@ def measured_traffic(cls, workload):
         return None
     return t["bytes_per_launch"]
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue rate the build can use: 256 CUs x 4 SIMDs x 16 lanes x 2 flop
+# (FMA) x 2.4 GHz; the published 157.3 TFLOP/s needs packed FP32, which the
+# build turns off
+VALU_FP32_PEAK_TFLOPS = 78.6
+# FP32 VALU work of one SAP colour pass per (site, field) with 4 MR steps on 4^4
+# blocks: the residual (8 hops of 180 flop with the boundary sign, the site
+# term 120, gamma5 r - D z 24), then per MR step the in-block hops (6 on
+# average, 168 flop each), the site term 120, the three block sums 144 and the
+# two updates 192, and z += e 24
+SAP_FLOP_PER_SITE_FIELD = 8 * 180 + 120 + 24 + 4 * (6 * 168 + 120 + 144 + 192) + 24
 
 # Workloads: lattice, field, aggregation, Nv, N_eig, tolerance.  Masses come
 # from tests/golden/m0.json (written by tests/golden/make_m0.py).
@@ -704,6 +715,16 @@ def main():
                      "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
                      "bytes_per_launch": round(k_bytes / max(k_launches, 1))},
     }
+    if args.roofline_class == "sap" and k_ms > 0 and wl["params"].get("sap_mr", 4) == 4:
+        # the pass's arithmetic intensity (about 19 flop per algorithmic byte) is
+        # above the FP32 VALU ridge (9.8): report the ALU fraction beside the HBM one.
+        # Site-field pairs from the bytes: (36 + 48 nf) complex FP32 per site of the colour
+        site_fields = (k_bytes / 8.0 - 36.0 * (V / 2) * k_launches) / 48.0
+        flops = SAP_FLOP_PER_SITE_FIELD * site_fields
+        tf = flops / (k_ms * 1e-3) / 1e12
+        out["roofline"]["alu"] = {"achieved": round(tf, 2), "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": round(tf / VALU_FP32_PEAK_TFLOPS, 4),
+                                  "flop_per_launch": round(flops / max(k_launches, 1))}
     # the same solve on the all-FP64 GPU path (smoother and coarse solves in FP64
     # too), after the timed steps: time and agreement of the eigenvalues
     if not args.no_fp64_compare and args.workload != "large":

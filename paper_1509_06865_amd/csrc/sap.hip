@@ -24,7 +24,7 @@ template <typename T> __device__ inline T wsumT(T v) {
 // faster than three waves without spills: 0.179 against 0.186 ms per 16-field
 // pass on 16^4).  With CLOV the site term carries the clover term.
 template <typename T, bool CLOV>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_sap_colour(Geom g, const cplx<T> *__restrict__ U,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_sap_colour(Geom g, const cplx<T> *__restrict__ U,
                                                     const cplx<T> *__restrict__ rin, cplx<T> *__restrict__ zio,
                                                     const int *__restrict__ blocks, T m0, Shifts sig, int n_mr,
                                                     int nrhs, const cplx<T> *__restrict__ C) {

@@ -138,21 +138,25 @@ def _dense_lowest(U, m0, dims, bc, n):
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
-def test_rqi_with_clover_lowest_eight_match_dense(prec):
+def test_rqi_with_clover_lowest_twelve_match_dense(prec):
+    # the periodic tiny lattice: with the clover term its 12 lowest |lambda|
+    # (0.12 .. 0.20) sit below a wide gap (next 0.80); the antiperiodic one has
+    # no gap at all near its lowest modes
     from paper_1509_06865_amd import Context, MGParams
-    cfg = json.load(open(os.path.join(GOLDEN, "m0.json")))["tiny_antiperiodic"]
+    cfg = json.load(open(os.path.join(GOLDEN, "m0.json")))["tiny_periodic"]
     dims, bc, m0 = tuple(cfg["dims"]), cfg["t_bc"], cfg["m0"]
-    print(f"[clover rqi] {dims}, 8 lowest, precision {prec}", flush=True)
+    n = 12
+    print(f"[clover rqi] {dims}, {n} lowest, precision {prec}", flush=True)
     U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
-    ref, op = _dense_lowest(U, m0, dims, bc, 8)
+    ref, op = _dense_lowest(U, m0, dims, bc, n)
     c = Context(dims, bc)
     Ud = dev(U)
     c.clover(Ud, CSW)
     c.mg_setup(Ud, m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(8, dims, 35)),
                MGParams(precision=prec, coarse_m=128, coarse_tol=1e-8, coarse_restarts=2, n_setup=4, rqi_block=4,
                         rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1))
-    # 8 pairs + 4 guard vectors: 4 start vectors beyond the 8 of the setup
-    lam, V, res, info = c.rqi_lowmodes(8, 1e-10, V0=dev(lqsynth.gaussian_spinors(4, dims, 37)))
+    # n pairs + 4 guard vectors: start vectors beyond the 8 of the setup
+    lam, V, res, info = c.rqi_lowmodes(n, 1e-10, V0=dev(lqsynth.gaussian_spinors(n + 4 - 8, dims, 37)))
     assert info["converged"], info
     lam = np.asarray(lam)
     order = np.lexsort((lam, np.abs(lam)))
@@ -160,7 +164,7 @@ def test_rqi_with_clover_lowest_eight_match_dense(prec):
     assert np.all(np.abs(lam - ref) <= 1e-10 * np.abs(ref)), (lam, ref)
     Vh = host(V)[order]
     Qv = op.Q(Vh)
-    assert max(np.linalg.norm(Qv[i] - lam[i] * Vh[i]) for i in range(8)) <= 2e-10
+    assert max(np.linalg.norm(Qv[i] - lam[i] * Vh[i]) for i in range(n)) <= 2e-10
 
 
 def test_lanczos_with_clover_lowest_eight_match_dense():
