@@ -108,6 +108,14 @@ typedef struct {
   int smooth1_m;        /* GMRES steps per level-1 smoothing step (gamma5^c form; a
                            fixed number, no convergence test) */
   int post1;            /* level-1 post-smoothing steps after the level-2 correction */
+  /* RQI solve effort for stragglers: a vector whose residual eps_i is below
+     rqi_stall_eps and fell by less than half over its last sweep gets
+     rqi_stall_restarts more FGMRES restarts in its next solve (its block is
+     solved apart from the others); 0 = off.  Near convergence RQI with a
+     loosely solved system converges linearly at the solve's residual
+     reduction, so a vector that has stopped gaining needs a better solve */
+  int rqi_stall_restarts;
+  double rqi_stall_eps;
 } lq_mg_params;
 
 typedef struct {

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1343,6 +1344,8 @@ int lq_params_default(lq_mg_params *p) {
   p->coarse2_tol = 0.1;
   p->smooth1_m = 4;
   p->post1 = 1;
+  p->rqi_stall_restarts = 0;
+  p->rqi_stall_eps = 1e-4;
   return LQ_OK;
 }
 
@@ -1462,6 +1465,7 @@ int mg_setup(lq_ctx *c, const lq_c128 *U, double m0, int n_levels, const int n_t
     if (p.graphs != 0 && p.graphs != 1) fail(LQ_ERR_ARG, "graphs must be 0 or 1");
     if (p.coarse_bf16 != 0 && p.coarse_bf16 != 1) fail(LQ_ERR_ARG, "coarse_bf16 must be 0 or 1");
     if (p.coarse_bf16 && p.precision != LQ_PREC_MIXED) fail(LQ_ERR_ARG, "coarse_bf16 needs LQ_PREC_MIXED");
+    if (p.rqi_stall_restarts < 0 || !(p.rqi_stall_eps >= 0)) fail(LQ_ERR_ARG, "mg_setup: bad straggler parameters");
     if (p.coarse_m < 1 || p.fgmres_m < 1 || p.sap_mr < 0 || p.post < 0 || p.pre < 0)
       fail(LQ_ERR_ARG, "bad iteration parameters");
     c->p = p;
@@ -1743,13 +1747,26 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
     std::vector<cd> Aop, Gop;
     bool ag_valid = false;
     bool done = false;
+    // residuals at the start of the previous sweep, by slot (stragglers)
+    std::vector<double> eps_prev(nw, std::numeric_limits<double>::infinity());
     while (!done && S.sweeps < c->p.rqi_max_sweeps) {
-      std::vector<int> todo;
-      for (int i = 0; i < nw; ++i)
-        if (eps[i] > tol) todo.push_back(i);
+      // unconverged vectors; stragglers (below rqi_stall_eps, less than halved
+      // over the last sweep) go last, in blocks of their own with more restarts
+      std::vector<int> todo, slow;
+      for (int i = 0; i < nw; ++i) {
+        if (!(eps[i] > tol)) continue;
+        const bool stalled = c->p.rqi_stall_restarts > 0 && eps[i] < c->p.rqi_stall_eps && eps[i] > 0.5 * eps_prev[i];
+        (stalled ? slow : todo).push_back(i);
+      }
+      const size_t n_fast = todo.size();
+      todo.insert(todo.end(), slow.begin(), slow.end());
+      eps_prev = eps;
       if (todo.empty()) break;
-      for (size_t q0 = 0; q0 < todo.size(); q0 += nb) {
-        const int nk = (int)std::min<size_t>(nb, todo.size() - q0);
+      for (size_t q0 = 0, step = 0; q0 < todo.size(); q0 += step) {
+        // blocks of nb, the last fast block cut short so no block mixes the two groups
+        const int nk = (int)std::min<size_t>(nb, (q0 < n_fast ? n_fast : todo.size()) - q0);
+        step = (size_t)nk;
+        const bool boost = q0 >= n_fast;
         std::vector<double> sig(nk);
         for (int q = 0; q < nk; ++q) {
           const int i = todo[q0 + q];
@@ -1770,8 +1787,8 @@ int rqi_lowmodes(lq_ctx *c, int n_eig, double tol, double *lambda, lq_c128 *Vout
         }
         int its[kMaxRhs];
         double rr[kMaxRhs];
-        solve_shifted(c, nk, sig.data(), B, X, c->p.rqi_solve_tol, its, rr, c->p.rqi_solve_restarts,
-                      c->p.rqi_deflate ? &D : nullptr);
+        solve_shifted(c, nk, sig.data(), B, X, c->p.rqi_solve_tol, its, rr,
+                      c->p.rqi_solve_restarts + (boost ? c->p.rqi_stall_restarts : 0), c->p.rqi_deflate ? &D : nullptr);
         for (int q = 0; q < nk; ++q) S.fgmres_iters += its[q];
         S.solves += nk;
         S.t_solve += now() - t0;

@@ -47,7 +47,8 @@ class _Params(C.Structure):
                 ("rayleigh_ritz", C.c_int), ("rqi_guard", C.c_int), ("rqi_solve_restarts", C.c_int),
                 ("rqi_deflate", C.c_int), ("rqi_start_passes", C.c_int), ("graphs", C.c_int),
                 ("coarse_bf16", C.c_int), ("coarse2_m", C.c_int), ("coarse2_restarts", C.c_int),
-                ("coarse2_tol", C.c_double), ("smooth1_m", C.c_int), ("post1", C.c_int)]
+                ("coarse2_tol", C.c_double), ("smooth1_m", C.c_int), ("post1", C.c_int),
+                ("rqi_stall_restarts", C.c_int), ("rqi_stall_eps", C.c_double)]
 
 
 class _SolveStats(C.Structure):
@@ -91,6 +92,8 @@ class MGParams:
     coarse2_tol: float | None = None
     smooth1_m: int | None = None
     post1: int | None = None
+    rqi_stall_restarts: int | None = None
+    rqi_stall_eps: float | None = None
 
     def to_c(self, lib) -> _Params:
         p = _Params()

@@ -594,6 +594,29 @@ def test_rqi_lowest_eight_match_dense(name, prec, nv, bf16):
     assert np.abs(G - np.eye(8)).max() < 1e-10
 
 
+def test_rqi_with_straggler_restarts_returns_the_same_pairs():
+    # the straggler rule (more FGMRES restarts for vectors that stop gaining,
+    # solved in blocks of their own) changes only how hard systems are solved:
+    # the tiny periodic workload's 8 lowest pairs, each to 1e-10 of the dense ones
+    from paper_1509_06865_amd import LQError, MGParams
+    dims, bc, eps, seed, m0 = tiny("tiny_periodic")
+    print("[rqi straggler restarts] 4^4 periodic, 8 lowest", flush=True)
+    U = lqsynth.gauge_field(dims, eps, seed)
+    c = _ctx(dims, bc)
+    c.mg_setup(dev(U), m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(8, dims, 102)),
+               MGParams(precision=1, coarse_m=64, coarse_tol=0.1, coarse_restarts=1, n_setup=4, rqi_block=4,
+                        rqi_max_sweeps=40, rqi_guard=4, rayleigh_ritz=1, rqi_solve_restarts=0,
+                        rqi_stall_restarts=3, rqi_stall_eps=1e-2))
+    lam, V, res, info = c.rqi_lowmodes(8, 1e-10, V0=dev(lqsynth.gaussian_spinors(4, dims, 103)))
+    assert info["converged"], info
+    ev = np.linalg.eigvalsh(dense_Q(U, m0, Lattice(dims, bc)))
+    ref = np.array(sorted(ev[np.argsort(np.abs(ev))][:8], key=lambda v: (abs(v), v)))
+    assert np.all(np.abs(np.array(lam) - ref) <= 1e-10 * np.abs(ref))
+    with pytest.raises(LQError):
+        c.mg_setup(dev(U), m0, (2, 2, 2, 2), dev(lqsynth.gaussian_spinors(8, dims, 102)),
+                   MGParams(rqi_stall_restarts=-1))
+
+
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
 def test_rqi_exactly_degenerate_free_field_shell(prec):
     # The method's degenerate case: unit links on a periodic 4^4 lattice.  The

@@ -42,6 +42,7 @@ def test_params_struct_matches_library_defaults():
     assert lib.lq_params_default(ctypes.byref(p)) == 0
     assert p.rqi_block == 16 and p.fgmres_m == 10 and abs(p.rqi_solve_tol - 1e-6) < 1e-20
     assert p.rqi_deflate == 1 and p.rayleigh_ritz == 1
+    assert p.rqi_stall_restarts == 0 and abs(p.rqi_stall_eps - 1e-4) < 1e-20
     assert lib.lq_params_default(None) == -1
 
 

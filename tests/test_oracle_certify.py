@@ -2,28 +2,20 @@
 tiny periodic lattice: the residual bound and the Kato-Temple bound hold for
 perturbed eigenvectors, and deflated inverse iteration finds the next mode
 after the exact lowest ones, or the missing one when a low mode is left out."""
-import json
-import os
 
 import numpy as np
 import pytest
-import scipy.linalg
 
-import lqsynth
 from oracle import certify as C
-from oracle.dirac import Lattice, WilsonOp, dense_Q
-
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "m0.json")
+from oracle.dirac import Lattice, WilsonOp
 
 
 @pytest.fixture(scope="module")
 def tiny():
-    cfg = json.load(open(GOLDEN))["tiny_periodic"]
+    from dense_spectra import tiny_periodic_dense
+    cfg, U, Qd, ev, vecs = tiny_periodic_dense()
     dims = tuple(cfg["dims"])
     lat = Lattice(dims, cfg["t_bc"])
-    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
-    Qd = dense_Q(U, cfg["m0"], lat)
-    ev, vecs = scipy.linalg.eigh(Qd)
     order = np.argsort(np.abs(ev), kind="stable")
     return dict(dims=dims, op=WilsonOp(U, cfg["m0"], lat), Qd=Qd, ev=ev[order], vecs=vecs[:, order])
 

@@ -5,28 +5,21 @@ the low part plus Q^{-1} R~ is exactly Q^{-1} (so the stochastic high part
 leaves the estimate unbiased); R~ annihilates Q V~; tr(Q Q~_low^{-1}) equals the
 number of modes; the per-timeslice loop and connected correlator of the low
 part equal their definitions written out with the dense low-mode matrix."""
-import json
-import os
 
 import numpy as np
 import pytest
-import scipy.linalg
 
 import lqsynth
 from oracle import lma
-from oracle.dirac import Lattice, WilsonOp, dense_Q
-
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "m0.json")
+from oracle.dirac import Lattice, WilsonOp
 
 
 @pytest.fixture(scope="module")
 def tiny():
-    cfg = json.load(open(GOLDEN))["tiny_periodic"]
+    from dense_spectra import tiny_periodic_dense
+    cfg, U, Qd, ev, vecs = tiny_periodic_dense()
     dims = tuple(cfg["dims"])
     lat = Lattice(dims, cfg["t_bc"])
-    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
-    Qd = dense_Q(U, cfg["m0"], lat)
-    ev, vecs = scipy.linalg.eigh(Qd)
     o = np.argsort(np.abs(ev), kind="stable")
     return dict(dims=dims, lat=lat, op=WilsonOp(U, cfg["m0"], lat), Qd=Qd, ev=ev[o], vecs=vecs[:, o],
                 T=dims[3], Vol=lat.V)

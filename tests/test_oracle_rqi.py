@@ -1,35 +1,26 @@
 """Pins of the oracle's Alg. 1 (RQI + multigrid) and Rayleigh-Ritz against the
 definition of the result: the eigenpairs of Hermitian Q with smallest |lambda|
 (dense eigendecomposition of the 3072 x 3072 matrix)."""
-import json
-import os
 
 import numpy as np
 import pytest
-import scipy.linalg
 
 import lqsynth
 from oracle import mg as M
 from oracle import rqi as R
-from oracle.dirac import Lattice, WilsonOp, dense_Q
-
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "m0.json")
+from oracle.dirac import Lattice, WilsonOp
 
 
 @pytest.fixture(scope="module")
 def tiny_periodic():
-    cfg = json.load(open(GOLDEN))["tiny_periodic"]
+    from dense_spectra import tiny_periodic_dense
+    cfg, U, Qd, ev, vecs = tiny_periodic_dense()
     dims = tuple(cfg["dims"])
     lat = Lattice(dims, cfg["t_bc"])
-    U = lqsynth.gauge_field(dims, cfg["eps"], cfg["field_seed"])
     m0 = cfg["m0"]
-    Qd = dense_Q(U, m0, lat)
-    ev = np.linalg.eigvalsh(Qd)
-    # eigenvectors of the 12 eigenvalues nearest zero only (an interval of the
-    # sorted spectrum); EV maps an index of ev to its eigenvector
+    # eigenvectors of the 12 eigenvalues nearest zero; EV maps an index of ev to its eigenvector
     near = np.sort(np.argsort(np.abs(ev))[:12])
-    _, vecs = scipy.linalg.eigh(Qd, subset_by_index=[int(near[0]), int(near[-1])])
-    EV = {int(near[0]) + k: vecs[:, k] for k in range(vecs.shape[1])}
+    EV = {int(i): vecs[:, int(i)] for i in near}
     return dict(dims=dims, lat=lat, U=U, m0=m0, ev=ev, EV=EV, op=WilsonOp(U, m0, lat))
 
 
