@@ -405,9 +405,22 @@ def learned_setup(args):
     ctx.mg_setup(U, m0, agg, phi0[:nv].contiguous(), plain)
     P_plain = ctx.get_interp()
     X = L.propose(ctx, U, net, phi0)
+    torch.cuda.synchronize()
+    a = time.time()
+    Xb = L.propose(ctx, U, net, phi0, bf16=True)        # the layers on the bfloat16 matrix cores
+    torch.cuda.synchronize()
+    t_bf16 = time.time() - a
+    a = time.time()
+    X = L.propose(ctx, U, net, phi0)
+    torch.cuda.synchronize()
+    t_fp64 = time.time() - a
     out["loss_vs_lowest24"] = {"network_outputs": L.loss_of(ctx, X, ref_V, agg),
+                               "network_outputs_bf16_layers": L.loss_of(ctx, Xb, ref_V, agg),
                                "plain_setup_P": L.loss_of(ctx, P_plain, ref_V, agg),
                                "random_start_vectors": L.loss_of(ctx, phi0, ref_V, agg)}
+    out["inference_s"] = {"fp64_direct": round(t_fp64, 3), "bf16_mfma": round(t_bf16, 3),
+                          "rel_diff": float(torch.linalg.norm(Xb - X) / torch.linalg.norm(X))}
+    del Xb
     del P_plain
     res = {}
     for name in ("plain", "learned"):
@@ -547,6 +560,48 @@ def lanczos_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def ptc_layer_mode(args):
+    """One 16 -> 16 parallel-transport layer of the learned setup on the 16^4
+    field: the direct FP64 kernel against the bfloat16 matrix-core form, mean
+    time of a few launches (HIP events through torch on the context's stream),
+    the work as a complex product (8 flop per complex multiply-add:
+    81 x (4 c_in) x (4 c_out) x 3 V) and the agreement of the two outputs.
+    Prints one JSON line."""
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import Context
+    gold = load_golden("medium")
+    dims = tuple(gold["dims"])
+    V = int(np.prod(dims))
+    cin = cout = 16
+    U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
+    phi = device_gaussian(cin, dims, 501, torch)
+    rng = np.random.default_rng(502)
+    W = torch.from_numpy((rng.standard_normal((cout, cin, 81, 4, 4)) +
+                          1j * rng.standard_normal((cout, cin, 81, 4, 4))) / 60).cuda()
+    ctx = Context(dims, gold["t_bc"])
+    flop = 8.0 * 81 * (4 * cin) * (4 * cout) * 3 * V
+    out = {"workload": f"16^4, {cin} -> {cout} channels, 81 offsets", "flop_per_layer": flop}
+    res = {}
+    for name, fn, reps in (("fp64_direct", ctx.ptc_forward, 2), ("bf16_mfma", ctx.ptc_forward_bf16, 10)):
+        y = fn(U, phi, W)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            y = fn(U, phi, W)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = y
+        out[name] = {"ms": round(ms, 3), "TFLOPs": round(flop / (ms * 1e-3) / 1e12, 2)}
+        log(f"ptc layer {name}: {ms:.3f} ms")
+    a, b = res["bf16_mfma"].cpu().numpy(), res["fp64_direct"].cpu().numpy()
+    out["rel_diff"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["bf16_frac_of_2500_TFLOPs"] = round(out["bf16_mfma"]["TFLOPs"] / 2500.0, 4)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -575,6 +630,8 @@ def main():
     ap.add_argument("--lma", action="store_true", help="approximate low-mode averaging on the 16^4 field")
     ap.add_argument("--lma-modes", type=int, default=20)
     ap.add_argument("--lma-noise", type=int, default=32)
+    ap.add_argument("--ptc-layer", action="store_true",
+                    help="time one 16 -> 16 layer of the learned setup: direct FP64 against bfloat16 matrix cores")
     ap.add_argument("--lanczos", action="store_true",
                     help="restarted Lanczos on Q^2 against RQI with the multigrid on the 16^4 field (sec. 2.2)")
     ap.add_argument("--lanczos-neig", default="20,50")
@@ -601,6 +658,9 @@ def main():
         return
     if args.lanczos:
         lanczos_mode(args)
+        return
+    if args.ptc_layer:
+        ptc_layer_mode(args)
         return
     if args.kernel_only:
         kernel_only(args)

@@ -314,6 +314,17 @@ int lanczos_lowmodes(lq_ctx *ctx, const lq_c128 *U, double m0, int n_eig, int n_
  * shapes.  Errors: LQ_ERR_ARG. */
 int lq_ptc_forward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
                    const lq_c128 *W, lq_c128 *out);
+/* The same layer on the bfloat16 matrix cores: weights, inputs and path
+ * products rounded to bfloat16 (8-bit mantissa), products accumulated in FP32
+ * (v_mfma_f32_16x16x16bf16), output written as complex128.  The layer as a
+ * product per offset d: M = 4 c_out rows (o, s), K = 4 c_in (i, t), N = 3 V
+ * columns (x, colour).  Arguments and layouts as lq_ptc_forward;
+ * 1 <= c_in, c_out <= 24; out must not overlap phi, U or W.  Allocates a
+ * scratch of 81 (4 c_out) (4 c_in) + 12 c_in V words on first use.  The result
+ * differs from lq_ptc_forward by the bfloat16 rounding (about 2^-9 relative
+ * per entry).  Errors: LQ_ERR_ARG, LQ_ERR_OOM. */
+int lq_ptc_forward_bf16(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
+                        const lq_c128 *W, lq_c128 *out);
 /* Gradients through lq_ptc_forward for a real loss L: given g_out =
  * dL/dRe(out) + i dL/dIm(out) (device [c_out][12][V]), writes g_in (device
  * [c_in][12][V]) and g_W (device [c_out][c_in][81][4][4]) of the same form for

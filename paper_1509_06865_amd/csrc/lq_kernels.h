@@ -182,6 +182,11 @@ void launch_coarse_parts2(const Level2Geom &g, const cplx<T> *Qc, const cplx<T> 
 // ---- parallel-transport convolution (ptc.hip) ---------------------------------
 // out[o] = sum_i sum_d W[o][i][d] T_d phi[i](. + d), canonical layout, FP64;
 // phi [cin][12][V], W [cout][cin][81][4][4], out [cout][12][V]
+// The same layer on the bfloat16 matrix cores (FP32 accumulation), 1 <= cin, cout <= 24;
+// scratch: ptc_bf16_scratch_words(V, cin, cout) 32-bit words (bfloat16 weights and inputs).
+size_t ptc_bf16_scratch_words(int V, int cin, int cout);
+void launch_ptc_forward_bf16(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
+                             c128 *out, unsigned *scratch, hipStream_t st);
 void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
                         hipStream_t st);
 // gradients of a real loss through the layer (g = dL/dRe out + i dL/dIm out): gin [cin][12][V]

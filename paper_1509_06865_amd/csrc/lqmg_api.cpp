@@ -165,6 +165,7 @@ struct lq_ctx {
   DevBuf<double> coarse_sig;        // shifts of the current coarse solve [kMaxRhs]
   DevBuf<bf16c> QcB;                // the FP32 Q_c in bfloat16 (coarse_bf16)
   DevBuf<double> net_scratch;       // per-site partial sums of the network's bias gradients
+  DevBuf<unsigned> ptc_bf16;        // bfloat16 weights and inputs of the matrix-core layer
   // third level (n_levels == 3): aggregates of the coarse lattice
   int n_levels = 2;
   int Nv2 = 0;
@@ -1916,6 +1917,19 @@ int lq_ptc_forward(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, in
       fail(LQ_ERR_ARG, "lq_ptc_forward: NULL pointer or channel count outside 1..64");
     launch_ptc_forward(c->gcan, (const c128 *)U, c_in, (const c128 *)phi, c_out, (const c128 *)W, (c128 *)out,
                        c->st);
+    return LQ_OK;
+  });
+}
+
+int lq_ptc_forward_bf16(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out, const lq_c128 *W,
+                        lq_c128 *out) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !phi || !W || !out || c_in < 1 || c_in > 24 || c_out < 1 || c_out > 24)
+      fail(LQ_ERR_ARG, "lq_ptc_forward_bf16: NULL pointer or channel count outside 1..24");
+    unsigned *sc = c->ptc_bf16.get(ptc_bf16_scratch_words(c->gcan.V, c_in, c_out));
+    launch_ptc_forward_bf16(c->gcan, (const c128 *)U, c_in, (const c128 *)phi, c_out, (const c128 *)W,
+                            (c128 *)out, sc, c->st);
     return LQ_OK;
   });
 }

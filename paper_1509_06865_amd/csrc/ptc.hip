@@ -414,6 +414,212 @@ __global__ void k_adam(long long n, double *__restrict__ p, const double *__rest
   p[e] -= (lr / bc1) * mi / (sqrt(vi) / sbc2 + eps);
 }
 
+// ---------------------------------------------------------------------------
+// GEMM form on the bfloat16 matrix cores (FP32 accumulation).  For one offset
+// d the layer is a complex product
+//   out[(o, s)][(x, a)] += sum_{(i, t)} W[o][i][d][s][t] (T_d(x) phi[i](x + d))[t][a]
+// with M = 4 c_out, K = 4 c_in and N = 3 x the sites.  One workgroup takes 32
+// sites (96 columns, six tiles of 16) and all output channels; per offset the
+// 32 path products are formed once (FP64, then rounded), the weights of d and
+// the transported inputs are staged in LDS as bfloat16 complex words, and
+// each wave accumulates its output tiles with v_mfma_f32_16x16x16bf16_1k on
+// the interleaved real embedding of the complex product (as the coarse apply:
+// lane l holds A[l % 16][4 (l / 16) + i] and B[4 (l / 16) + i][l % 16]).
+// Weights and inputs are rounded to bfloat16 once, before the launch.
+constexpr int kPtcMaxCh = 24;                    // channels per layer on this path
+constexpr int kPtcSites = 32;                    // sites per workgroup
+constexpr int kPtcRows = 4 * kPtcMaxCh;          // complex rows (o, s) / K entries (i, t)
+constexpr int kPtcCols = 3 * kPtcSites;          // complex columns (x, a)
+constexpr int kPtcTiles = (kPtcRows / 8) * (kPtcCols / 16) / 4;   // output tiles per wave (of 4)
+
+__device__ inline unsigned short bf16_of(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ inline unsigned bf16_word(double re, double im) {
+  return (unsigned)bf16_of((float)re) | ((unsigned)bf16_of((float)im) << 16);
+}
+
+__device__ inline float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+// weights as bfloat16 words [81][mrows][kcols]: row (o, s), column (i, t), zero padded
+__global__ void k_ptc_weights_bf16(const c128 *__restrict__ W, int cin, int cout, int mrows, int kcols,
+                                   unsigned *__restrict__ Wb) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)kPtcOffsets * mrows * kcols;
+  if (e >= n) return;
+  const int k = (int)(e / ((long long)mrows * kcols));
+  const int rem = (int)(e - (long long)k * mrows * kcols);
+  const int r = rem / kcols, c = rem - r * kcols;
+  const int o = r >> 2, s = r & 3, i = c >> 2, t = c & 3;
+  unsigned v = 0;
+  if (o < cout && i < cin) {
+    const c128 w = W[(((long long)o * cin + i) * kPtcOffsets + k) * 16 + 4 * s + t];
+    v = bf16_word(w.re, w.im);
+  }
+  Wb[e] = v;
+}
+
+// inputs as bfloat16 words, same layout [cin][12][V]
+__global__ void k_fields_bf16(const c128 *__restrict__ x, long long n, unsigned *__restrict__ y) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = bf16_word(x[e].re, x[e].im);
+}
+
+// T_d(x) in FP32 (the links rounded once): the path of path_transport
+__device__ inline int path_transport_f(const Geom &g, const c128 *__restrict__ U, int x, const int d[4], c64 T[9]) {
+  const long long V = g.V;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) T[e] = c64{(e % 4 == 0) ? 1.f : 0.f, 0.f};
+  int pos = x;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (d[mu] == 0) continue;
+    const SiteCoord c = decode(g, pos);
+    float sg;
+    bool in;
+    const int nxt = neighbour(g, pos, c, mu, d[mu] > 0, &sg, &in);
+    const int ls = d[mu] > 0 ? pos : nxt;
+    c64 L[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      // U_mu(pos) for a forward step, U_mu(pos - mu)^dag for a backward one
+      const int src = d[mu] > 0 ? e : 3 * (e % 3) + e / 3;
+      const c128 m = U[(long long)(mu * 9 + src) * V + ls];
+      L[e] = c64{sg * (float)m.re, sg * (d[mu] > 0 ? (float)m.im : -(float)m.im)};
+    }
+    c64 P[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) P[3 * a + b] = T[3 * a] * L[b] + T[3 * a + 1] * L[3 + b] + T[3 * a + 2] * L[6 + b];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) T[e] = P[e];
+    pos = nxt;
+  }
+  return pos;
+}
+
+typedef short v4s_ptc __attribute__((ext_vector_type(4)));
+typedef float v4f_ptc __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_ptc_forward_bf16(Geom g, const c128 *__restrict__ U, int cin, int cout,
+                                                          int mrows, int kcols, const unsigned *__restrict__ phib,
+                                                          const unsigned *__restrict__ Wb, c128 *__restrict__ out) {
+  __shared__ unsigned As[kPtcRows * (kPtcRows + 1)];
+  __shared__ unsigned Bs[kPtcRows * (kPtcCols + 1)];
+  __shared__ float Ts[kPtcSites][18];
+  __shared__ int Ps[kPtcSites];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int x0 = blockIdx.x * kPtcSites;
+  const long long V = g.V;
+  const int lda = kPtcRows + 1, ldb = kPtcCols + 1;
+  const int nt = kPtcCols / 16, ntiles = (mrows / 8) * nt;
+  const int kq = lane >> 4, ri = lane & 1;
+  v4f_ptc acc[kPtcTiles];
+#pragma unroll
+  for (int q = 0; q < kPtcTiles; ++q) acc[q] = v4f_ptc{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < kPtcOffsets; ++k) {
+    __syncthreads();                           // the previous offset's products are done with As, Bs
+    if (t < kPtcSites) {
+      int d[4];
+      offset_of(k, d);
+      const int x = x0 + t;
+      c64 T[9];
+      int pos = 0;
+      if (x < g.V) {
+        pos = path_transport_f(g, U, x, d, T);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) T[e] = c64{0.f, 0.f};
+      }
+#pragma unroll
+      for (int e = 0; e < 9; ++e) { Ts[t][2 * e] = T[e].re; Ts[t][2 * e + 1] = T[e].im; }
+      Ps[t] = pos;
+    }
+    const unsigned *wk = Wb + (long long)k * mrows * kcols;
+    for (int e = t; e < mrows * kcols; e += blockDim.x) {
+      const int r = e / kcols, c = e - r * kcols;
+      As[r * lda + c] = wk[e];
+    }
+    __syncthreads();
+    // transported inputs of (site, channel) pairs: Bs[(i, t)][(x, a)]
+    for (int e = t; e < kPtcSites * (kcols >> 2); e += blockDim.x) {
+      const int xs = e % kPtcSites, i = e / kPtcSites;
+      float qr[12], qi[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) { qr[c] = 0.f; qi[c] = 0.f; }
+      if (i < cin && x0 + xs < g.V) {
+        const unsigned *p = phib + (long long)i * 12 * V + Ps[xs];
+        float pr[12], pi[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const unsigned wv = p[(long long)c * V];
+          pr[c] = bf16_lo(wv);
+          pi[c] = bf16_hi(wv);
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const float tr = Ts[xs][2 * (3 * a + b)], ti = Ts[xs][2 * (3 * a + b) + 1];
+              re += tr * pr[3 * sp + b] - ti * pi[3 * sp + b];
+              im += tr * pi[3 * sp + b] + ti * pr[3 * sp + b];
+            }
+            qr[3 * sp + a] = re;
+            qi[3 * sp + a] = im;
+          }
+      }
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          Bs[(4 * i + sp) * ldb + 3 * xs + a] = bf16_word(qr[3 * sp + a], qi[3 * sp + a]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPtcTiles; ++q) {
+      const int tile = w + 4 * q;
+      if (tile < ntiles) {                     // uniform per wave
+        const int rt = tile / nt, ct = tile - rt * nt;
+        const int crow = 8 * rt + ((lane & 15) >> 1), col = 16 * ct + (lane & 15);
+        for (int st = 0; st < (kcols >> 3); ++st) {
+          const int cj = 8 * st + 2 * kq;
+          const unsigned m0 = As[crow * lda + cj], m1 = As[crow * lda + cj + 1];
+          // Re row: (Mr, -Mi); Im row: (Mi, Mr)
+          const unsigned a0 = ri ? ((m0 >> 16) | (m0 << 16)) : (m0 ^ 0x80000000u);
+          const unsigned a1 = ri ? ((m1 >> 16) | (m1 << 16)) : (m1 ^ 0x80000000u);
+          const unsigned b0 = Bs[cj * ldb + col], b1 = Bs[(cj + 1) * ldb + col];
+          v4s_ptc av, bv;
+          av[0] = (short)(a0 & 0xffffu); av[1] = (short)(a0 >> 16); av[2] = (short)(a1 & 0xffffu); av[3] = (short)(a1 >> 16);
+          bv[0] = (short)(b0 & 0xffffu); bv[1] = (short)(b0 >> 16); bv[2] = (short)(b1 & 0xffffu); bv[3] = (short)(b1 >> 16);
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // acc[q][r] = D[4 kq + r][col]: complex row 8 rt + 2 kq + (r >> 1), Re/Im = r & 1
+#pragma unroll
+  for (int q = 0; q < kPtcTiles; ++q) {
+    const int tile = w + 4 * q;
+    if (tile < ntiles) {
+      const int rt = tile / nt, ct = tile - rt * nt;
+      const int col = 16 * ct + (lane & 15);
+      const int xs = col / 3, a = col - 3 * xs, x = x0 + xs;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int crow = 8 * rt + 2 * kq + h, o = crow >> 2, sp = crow & 3;
+        if (o < cout && x < g.V) out[((long long)o * 12 + 3 * sp + a) * V + x] = c128{acc[q][2 * h], acc[q][2 * h + 1]};
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void launch_adam(long long n, double *p, const double *g, double *m, double *v, double lr, double b1, double b2,
@@ -474,6 +680,25 @@ void launch_ptc_backward(const Geom &g, const c128 *U, int cin, const c128 *phi,
 void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_ptc_forward, dim3(blocks_for(g.V, 256), cout), dim3(256), 0, st, g, U, cin, phi, W, out);
+  LQ_HIP(hipGetLastError());
+}
+
+size_t ptc_bf16_scratch_words(int V, int cin, int cout) {
+  const int mrows = ((cout + 1) / 2) * 8, kcols = ((cin + 1) / 2) * 8;
+  return (size_t)kPtcOffsets * mrows * kcols + (size_t)cin * 12 * V;
+}
+
+void launch_ptc_forward_bf16(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
+                             c128 *out, unsigned *scratch, hipStream_t st) {
+  const int mrows = ((cout + 1) / 2) * 8, kcols = ((cin + 1) / 2) * 8;
+  unsigned *Wb = scratch, *phib = scratch + (size_t)kPtcOffsets * mrows * kcols;
+  const long long nw = (long long)kPtcOffsets * mrows * kcols, nf = (long long)cin * 12 * g.V;
+  hipLaunchKernelGGL(k_ptc_weights_bf16, dim3(blocks_for(nw, 256)), dim3(256), 0, st, W, cin, cout, mrows, kcols, Wb);
+  LQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_fields_bf16, dim3(blocks_for(nf, 256)), dim3(256), 0, st, phi, nf, phib);
+  LQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_ptc_forward_bf16, dim3(blocks_for(g.V, kPtcSites)), dim3(256), 0, st, g, U, cin, cout, mrows,
+                     kcols, phib, Wb, out);
   LQ_HIP(hipGetLastError());
 }
 

@@ -97,9 +97,10 @@ def train_step(ctx: Context, U, net: Network, phi0, targets, agg, lr: float):
     return ctx.lcnn_train_step(U, phi0, net.weights, net.biases, targets, agg, net.state, lr, net.step)
 
 
-def propose(ctx: Context, U, net: Network, phi0):
-    """The network's test vectors for field U from the start vectors phi0."""
-    return ctx.lcnn_forward(U, phi0, net.weights, net.biases)
+def propose(ctx: Context, U, net: Network, phi0, bf16: bool = False):
+    """The network's test vectors for field U from the start vectors phi0
+    (bf16: the layers on the bfloat16 matrix cores)."""
+    return ctx.lcnn_forward(U, phi0, net.weights, net.biases, bf16=bf16)
 
 
 def loss_of(ctx: Context, X, targets, agg):

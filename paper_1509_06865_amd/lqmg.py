@@ -26,7 +26,7 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
             "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc", "mg_info2",
             "mg_get_level2", "lma_low", "lma_high", "lq_timeslice_products", "lanczos_lowmodes",
-            "lq_clover"]
+            "lq_clover", "lq_ptc_forward_bf16"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -133,6 +133,7 @@ def load():
         "lq_timeslice_products": (i, [vp, i, vp, i, vp, vp]),
         "lanczos_lowmodes": (i, [vp, vp, d, i, i, i, d, i, vp, dp, vp, dp, ip]),
         "lq_clover": (i, [vp, vp, d]),
+        "lq_ptc_forward_bf16": (i, [vp, vp, i, vp, i, vp, vp]),
         "mg_get_level2": (i, [vp, vp, vp]),
         "mg_solve_shifted": (i, [vp, i, dp, vp, vp, d, C.POINTER(_SolveStats)]),
         "rqi_lowmodes": (i, [vp, i, d, dp, vp, dp, vp, i, C.POINTER(_RQIStats)]),
@@ -254,6 +255,15 @@ class Context:
                                             _ptr(out)))
         return out
 
+    def ptc_forward_bf16(self, U: torch.Tensor, phi: torch.Tensor, W: torch.Tensor):
+        """The same layer on the bfloat16 matrix cores (FP32 accumulation), c_in, c_out <= 24."""
+        c_in, c_out = int(phi.shape[0]), int(W.shape[0])
+        self._net_args(U, phi, W, c_in, c_out)
+        out = torch.empty((c_out,) + tuple(phi.shape[1:]), dtype=phi.dtype, device=phi.device)
+        self._check(self.lib.lq_ptc_forward_bf16(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
+                                                 _ptr(out)))
+        return out
+
     def ptc_backward(self, U: torch.Tensor, phi: torch.Tensor, W: torch.Tensor, g_out: torch.Tensor):
         """Gradients (same form as g_out = dL/dRe out + i dL/dIm out) of a real
         loss with respect to phi and W through one layer."""
@@ -356,12 +366,14 @@ class Context:
             self.adam_step(p, g, m, v, lr, t=t)
         return loss
 
-    def lcnn_forward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases):
+    def lcnn_forward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases, bf16: bool = False):
         """The learned setup's network on the device: the layers and the
-        nonlinearities in turn (each a library call)."""
+        nonlinearities in turn (each a library call); bf16 runs the layers on
+        the bfloat16 matrix cores (inference; widths up to 24)."""
         phi = phi0
+        layer_fn = self.ptc_forward_bf16 if bf16 else self.ptc_forward
         for layer, W in enumerate(weights):
-            phi = self.ptc_forward(U, phi, W)
+            phi = layer_fn(U, phi, W)
             if layer < len(weights) - 1:
                 phi = self.mod_relu(phi, biases[layer])
         return phi

@@ -150,6 +150,56 @@ def test_ptc_layer_matches_oracle(t_bc):
     assert relmax(g5 * yd[0], q[0]) < 1e-13
 
 
+def _cos_rel(y, ref):
+    num = abs(np.vdot(ref.ravel(), y.ravel()))
+    cos = num / (np.linalg.norm(y) * np.linalg.norm(ref))
+    return cos, np.linalg.norm(y - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("t_bc", [-1, 1])
+def test_ptc_layer_bf16_matches_oracle(t_bc):
+    # the layer on the bfloat16 matrix cores against the oracle's FP64 layer:
+    # norm-relative error <= 3e-2 and cosine >= 0.999 (the bfloat16 bar), with
+    # the rounding visibly present; 120 sites leave a ragged workgroup of 32
+    from oracle import lcnn
+    dims = (6, 2, 2, 5)
+    lat = Lattice(dims, t_bc)
+    U = lqsynth.gauge_field(dims, 0.4, 94)
+    phi = lqsynth.gaussian_spinors(3, dims, 95)
+    rng = np.random.default_rng(96)
+    W = (rng.standard_normal((5, 3, 81, 4, 4)) + 1j * rng.standard_normal((5, 3, 81, 4, 4))) / 30
+    ref = lcnn.forward(lcnn.transports(U, lat), torch.from_numpy(phi), [torch.from_numpy(W)], []).numpy()
+    c = _ctx(dims, t_bc)
+    y = host(c.ptc_forward_bf16(dev(U), dev(phi), dev(W)))
+    cos, rel = _cos_rel(y, ref)
+    assert rel <= 3e-2 and cos >= 0.999, (rel, cos)
+    assert rel > 1e-5                                   # bfloat16 rounding is present
+    # with the hopping weights the layer is D
+    Wd = lcnn.wilson_weights(-0.3).numpy()
+    yd = host(c.ptc_forward_bf16(dev(U), dev(phi[:1]), dev(Wd)))
+    q = host(c.q_apply(dev(U), -0.3, dev(phi[:1])))
+    g5 = np.array([1.0] * 6 + [-1.0] * 6)[:, None]
+    cos, rel = _cos_rel(g5 * yd[0], q[0])
+    assert rel <= 3e-2 and cos >= 0.999, (rel, cos)
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 16), (24, 16), (16, 24), (7, 9)])
+def test_ptc_layer_bf16_at_network_widths(cin, cout):
+    # the network's widths (24 -> 16 -> 16 -> 16 -> 24) and an odd pair, on 8^4,
+    # against the direct FP64 layer (itself equal to the oracle to 1e-13)
+    dims = (8, 8, 8, 8)
+    print(f"[ptc bf16] {cin} -> {cout} on 8^4", flush=True)
+    U = dev(lqsynth.gauge_field(dims, 0.3, 97))
+    phi = dev(lqsynth.gaussian_spinors(cin, dims, 98))
+    rng = np.random.default_rng(99)
+    W = dev((rng.standard_normal((cout, cin, 81, 4, 4)) + 1j * rng.standard_normal((cout, cin, 81, 4, 4))) / 60)
+    c = _ctx(dims, 1)
+    ref = host(c.ptc_forward(U, phi, W))
+    y = host(c.ptc_forward_bf16(U, phi, W))
+    cos, rel = _cos_rel(y, ref)
+    assert rel <= 3e-2 and cos >= 0.999, (rel, cos)
+
+
 @pytest.mark.parametrize("t_bc", [-1, 1])
 def test_ptc_layer_gradients_match_oracle_autograd(t_bc):
     # the layer's input and weight gradients for L = Re sum conj(G) out against
