@@ -379,7 +379,7 @@ def learned_setup(args):
         t_targets += time.time() - a
         a = time.time()
         for _ in range(args.train_steps):
-            losses.append(L.train_step(ctx, U, net, phi0, tgt, agg, args.train_lr))
+            losses.append(L.train_step(ctx, U, net, phi0, tgt, agg, args.train_lr, bf16=args.train_bf16))
         torch.cuda.synchronize()
         t_train += time.time() - a
         log(f"field {j + 1}/{n_fields}: eps {eps:.3f} m0 {m0:.4f} targets converged {info['converged']} "
@@ -398,6 +398,7 @@ def learned_setup(args):
     learned = MGParams(**dict(base, n_setup=args.learned_n_setup, n_init=0))
     V0 = device_gaussian(n_eig + guard - nv, dims, gold["field_seed"] + 2, torch)
     out = {"train": {"fields": n_fields, "steps_per_field": args.train_steps, "lr": args.train_lr,
+                     "layers": "bf16_mfma" if args.train_bf16 else "fp64_direct",
                      "first_loss": losses[0], "last_loss": losses[-1],
                      "mean_loss_first_10": float(np.mean(losses[:10])), "mean_loss_last_10": float(np.mean(losses[-10:])),
                      "targets_s": round(t_targets, 1), "train_s": round(t_train, 1)}}
@@ -429,7 +430,8 @@ def learned_setup(args):
                                                          wl["tol"], V0)
             info = dict(info, setup_s=ts, rqi_s=tr)
         else:
-            lam, Vv, r, info = L.learned_solve(ctx, U, m0, agg, net, phi0, learned, plain, n_eig, wl["tol"], V0, nv)
+            lam, Vv, r, info = L.learned_solve(ctx, U, m0, agg, net, phi0, learned, plain, n_eig, wl["tol"], V0, nv,
+                                               bf16=args.train_bf16)
         res[name] = {"converged": info["converged"], "sweeps": info["sweeps"], "solves": info["solves"],
                      "fgmres_iters": info["fgmres_iters"], "setup_s": round(info["setup_s"], 3),
                      "rqi_s": round(info["rqi_s"], 3), "max_residual": float(max(r)),
@@ -599,6 +601,25 @@ def ptc_layer_mode(args):
     a, b = res["bf16_mfma"].cpu().numpy(), res["fp64_direct"].cpu().numpy()
     out["rel_diff"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
     out["bf16_frac_of_2500_TFLOPs"] = round(out["bf16_mfma"]["TFLOPs"] / 2500.0, 4)
+    # the backward: input and weight gradients, twice the forward's products
+    G = device_gaussian(cout, dims, 503, torch)
+    bwd = {}
+    for name, fn, reps in (("fp64_direct", ctx.ptc_backward, 1), ("bf16_mfma", ctx.ptc_backward_bf16, 5)):
+        g = fn(U, phi, W, G)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g = fn(U, phi, W, G)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        bwd[name] = g
+        out["backward_" + name] = {"ms": round(ms, 3), "TFLOPs": round(2 * flop / (ms * 1e-3) / 1e12, 2)}
+        log(f"ptc layer backward {name}: {ms:.3f} ms")
+    for k, part in enumerate(("g_in", "g_W")):
+        a, b = bwd["bf16_mfma"][k].cpu().numpy(), bwd["fp64_direct"][k].cpu().numpy()
+        out[f"backward_rel_diff_{part}"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
     print(json.dumps(out), flush=True)
 
 
@@ -627,6 +648,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1)
     ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--learned-n-setup", type=int, default=1)
+    ap.add_argument("--train-bf16", action="store_true",
+                    help="train (and propose the learned setup's vectors) with the layers on the bfloat16 matrix cores")
     ap.add_argument("--lma", action="store_true", help="approximate low-mode averaging on the 16^4 field")
     ap.add_argument("--lma-modes", type=int, default=20)
     ap.add_argument("--lma-noise", type=int, default=32)

@@ -334,6 +334,20 @@ int lq_ptc_forward_bf16(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *
  * Errors: LQ_ERR_ARG. */
 int lq_ptc_backward(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
                     const lq_c128 *W, const lq_c128 *g_out, lq_c128 *g_in, lq_c128 *g_W);
+/* The same gradients on the bfloat16 matrix cores: g_out, W and phi rounded
+ * to bfloat16, the path products formed in FP32, products accumulated in
+ * FP32.  g_in is the adjoint layer (M = 4 c_in rows (i, t), K = 4 c_out, the
+ * conjugated weights and the back-transported g_out); g_W is, per offset, the
+ * product of g_out (rows (o, s), K = 3 V) with the conjugated transported
+ * inputs (columns (i, t)), summed by site chunks of about 2048 sites in FP32
+ * and the chunk sums added in a fixed order in FP64.  Arguments, layouts and
+ * aliasing rules as lq_ptc_backward; 1 <= c_in, c_out <= 24.  Allocates (on
+ * first use, shared with lq_ptc_forward_bf16) a scratch of 12 (c_in + c_out) V
+ * + 81 (4 c_in)(4 c_out) words + 2 n_chunks (the g_W size) floats.  The
+ * results differ from lq_ptc_backward by the bfloat16 rounding.  Errors:
+ * LQ_ERR_ARG, LQ_ERR_OOM. */
+int lq_ptc_backward_bf16(lq_ctx *ctx, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out,
+                         const lq_c128 *W, const lq_c128 *g_out, lq_c128 *g_in, lq_c128 *g_W);
 /* The network's nonlinearity between layers (gauge invariant): for channel c
  * and site x, out[c](x) = phi[c](x) * max(|phi[c](x)| + b[c], 0) / |phi[c](x)|,
  * |.| the norm over the 12 spin-colour components (out = 0 where phi = 0).

@@ -187,6 +187,12 @@ void launch_coarse_parts2(const Level2Geom &g, const cplx<T> *Qc, const cplx<T> 
 size_t ptc_bf16_scratch_words(int V, int cin, int cout);
 void launch_ptc_forward_bf16(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
                              c128 *out, unsigned *scratch, hipStream_t st);
+// The layer's gradients on the bfloat16 matrix cores (input gradient: the adjoint
+// product; weight gradient: per-offset products summed over site chunks); gin or
+// gW may be null; scratch: ptc_bf16_backward_scratch_words(V, cin, cout) words.
+size_t ptc_bf16_backward_scratch_words(int V, int cin, int cout);
+void launch_ptc_backward_bf16(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
+                              const c128 *gout, c128 *gin, c128 *gW, unsigned *scratch, hipStream_t st);
 void launch_ptc_forward(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W, c128 *out,
                         hipStream_t st);
 // gradients of a real loss through the layer (g = dL/dRe out + i dL/dIm out): gin [cin][12][V]

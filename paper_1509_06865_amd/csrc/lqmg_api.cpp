@@ -1946,6 +1946,20 @@ int lq_ptc_backward(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, i
   });
 }
 
+int lq_ptc_backward_bf16(lq_ctx *c, const lq_c128 *U, int c_in, const lq_c128 *phi, int c_out, const lq_c128 *W,
+                         const lq_c128 *g_out, lq_c128 *g_in, lq_c128 *g_W) {
+  return guard(c, [&] {
+    check_ctx(c);
+    if (!U || !phi || !W || !g_out || c_in < 1 || c_in > 24 || c_out < 1 || c_out > 24)
+      fail(LQ_ERR_ARG, "lq_ptc_backward_bf16: NULL pointer or channel count outside 1..24");
+    if (!g_in && !g_W) return LQ_OK;
+    unsigned *sc = c->ptc_bf16.get(ptc_bf16_backward_scratch_words(c->gcan.V, c_in, c_out));
+    launch_ptc_backward_bf16(c->gcan, (const c128 *)U, c_in, (const c128 *)phi, c_out, (const c128 *)W,
+                             (const c128 *)g_out, (c128 *)g_in, (c128 *)g_W, sc, c->st);
+    return LQ_OK;
+  });
+}
+
 int lq_mod_relu(lq_ctx *c, int channels, const lq_c128 *phi, const double *b, lq_c128 *out) {
   return guard(c, [&] {
     check_ctx(c);

@@ -12,6 +12,7 @@
 // This is the direct form: one thread per (site, output channel), the path
 // products formed on the fly, FP64.  It is the correctness reference on the
 // device for the GEMM-shaped (MFMA) form the layer takes at scale.
+#include <algorithm>
 #include "lq_kernels.h"
 #include "lq_dslash.h"
 
@@ -445,7 +446,10 @@ __device__ inline unsigned bf16_word(double re, double im) {
 __device__ inline float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
-// weights as bfloat16 words [81][mrows][kcols]: row (o, s), column (i, t), zero padded
+// weights as bfloat16 words [81][mrows][kcols], zero padded: row (o, s) and
+// column (i, t) for the layer; for its adjoint (ADJ, the input gradient) row
+// (i, t), column (o, s) and the entry conjugated (W^dag per spin block)
+template <bool ADJ>
 __global__ void k_ptc_weights_bf16(const c128 *__restrict__ W, int cin, int cout, int mrows, int kcols,
                                    unsigned *__restrict__ Wb) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -454,11 +458,12 @@ __global__ void k_ptc_weights_bf16(const c128 *__restrict__ W, int cin, int cout
   const int k = (int)(e / ((long long)mrows * kcols));
   const int rem = (int)(e - (long long)k * mrows * kcols);
   const int r = rem / kcols, c = rem - r * kcols;
-  const int o = r >> 2, s = r & 3, i = c >> 2, t = c & 3;
+  const int o = ADJ ? (c >> 2) : (r >> 2), s = ADJ ? (c & 3) : (r & 3);
+  const int i = ADJ ? (r >> 2) : (c >> 2), t = ADJ ? (r & 3) : (c & 3);
   unsigned v = 0;
   if (o < cout && i < cin) {
     const c128 w = W[(((long long)o * cin + i) * kPtcOffsets + k) * 16 + 4 * s + t];
-    v = bf16_word(w.re, w.im);
+    v = bf16_word(w.re, ADJ ? -w.im : w.im);
   }
   Wb[e] = v;
 }
@@ -505,6 +510,10 @@ __device__ inline int path_transport_f(const Geom &g, const c128 *__restrict__ U
 typedef short v4s_ptc __attribute__((ext_vector_type(4)));
 typedef float v4f_ptc __attribute__((ext_vector_type(4)));
 
+// ADJ: the input gradient, g_in[i](y) = sum_o sum_d W[o][i][d]^dag T_d(y - d)^dag g[o](y - d):
+// rows (i, t), K (o, s), the transported field T_d(y - d)^dag g[o](y - d).
+// cin here is the channel count of the field read (K), cout that of the output (rows).
+template <bool ADJ>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_ptc_forward_bf16(Geom g, const c128 *__restrict__ U, int cin, int cout,
                                                           int mrows, int kcols, const unsigned *__restrict__ phib,
                                                           const unsigned *__restrict__ Wb, c128 *__restrict__ out) {
@@ -530,7 +539,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       c64 T[9];
       int pos = 0;
       if (x < g.V) {
-        pos = path_transport_f(g, U, x, d, T);
+        if (ADJ) {
+          pos = back_offset(g, x, d);                    // the path from x - d ends at x
+          (void)path_transport_f(g, U, pos, d, T);
+        } else {
+          pos = path_transport_f(g, U, x, d, T);
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < 9; ++e) T[e] = c64{0.f, 0.f};
@@ -567,7 +581,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             float re = 0.f, im = 0.f;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-              const float tr = Ts[xs][2 * (3 * a + b)], ti = Ts[xs][2 * (3 * a + b) + 1];
+              // T[a][b] for the layer, conj(T[b][a]) for its adjoint
+              const int te = ADJ ? 3 * b + a : 3 * a + b;
+              const float tr = Ts[xs][2 * te], ti = ADJ ? -Ts[xs][2 * te + 1] : Ts[xs][2 * te + 1];
               re += tr * pr[3 * sp + b] - ti * pi[3 * sp + b];
               im += tr * pi[3 * sp + b] + ti * pr[3 * sp + b];
             }
@@ -618,6 +634,148 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       }
     }
   }
+}
+
+// The weight gradient on the bfloat16 matrix cores, per offset d a complex product
+//   gW[o][i][d][s][t] = sum_x sum_a g[o](x)[s][a] conj((T_d(x) phi[i](x + d))[t][a])
+// with M = 4 c_out rows (o, s), N = 4 c_in columns (i, t) and K = 3 V (site, colour).
+// Workgroup (chunk, d) runs over its chunk of sites 32 at a time (K = 96 per step:
+// the output gradients and the conjugated transported inputs staged in LDS) and
+// writes its FP32 sums; k_ptc_gw_sum adds the chunks in a fixed order.
+constexpr int kPtcGwCols = 4 * kPtcMaxCh;        // complex columns (i, t)
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_ptc_grad_weight_bf16(Geom g, const c128 *__restrict__ U, int cin, int cout, int mrows, int ncols, int chunk,
+                       const unsigned *__restrict__ phib, const unsigned *__restrict__ gb, float2 *__restrict__ part) {
+  __shared__ unsigned As[kPtcRows * (kPtcCols + 1)];
+  __shared__ unsigned Bs[kPtcCols * (kPtcGwCols + 1)];
+  __shared__ float Ts[kPtcSites][18];
+  __shared__ int Ps[kPtcSites];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int k = blockIdx.y, ch = blockIdx.x;
+  const int lo = ch * chunk, hi = min(lo + chunk, g.V);
+  const long long V = g.V;
+  const int lda = kPtcCols + 1, ldb = kPtcGwCols + 1;
+  const int nt = ncols / 16, ntiles = (mrows / 8) * nt;
+  const int kq = lane >> 4, ri = lane & 1;
+  int d[4];
+  offset_of(k, d);
+  v4f_ptc acc[kPtcTiles];
+#pragma unroll
+  for (int q = 0; q < kPtcTiles; ++q) acc[q] = v4f_ptc{0.f, 0.f, 0.f, 0.f};
+  for (int x0 = lo; x0 < hi; x0 += kPtcSites) {
+    __syncthreads();                           // the previous step's products are done with As, Bs
+    if (t < kPtcSites) {
+      const int x = x0 + t;
+      c64 T[9];
+      int pos = 0;
+      if (x < hi) {
+        pos = path_transport_f(g, U, x, d, T);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) T[e] = c64{0.f, 0.f};
+      }
+#pragma unroll
+      for (int e = 0; e < 9; ++e) { Ts[t][2 * e] = T[e].re; Ts[t][2 * e + 1] = T[e].im; }
+      Ps[t] = pos;
+    }
+    // output gradients: As[(o, s)][(x, a)]
+    for (int e = t; e < kPtcSites * (mrows >> 2); e += blockDim.x) {
+      const int xs = e % kPtcSites, o = e / kPtcSites, x = x0 + xs;
+      const bool live = o < cout && x < hi;
+      const unsigned *p = gb + (long long)o * 12 * V + x;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) As[(4 * o + c / 3) * lda + 3 * xs + c % 3] = live ? p[(long long)c * V] : 0u;
+    }
+    __syncthreads();
+    // conjugated transported inputs: Bs[(x, a)][(i, t)]
+    for (int e = t; e < kPtcSites * (ncols >> 2); e += blockDim.x) {
+      const int xs = e % kPtcSites, i = e / kPtcSites;
+      float qr[12], qi[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) { qr[c] = 0.f; qi[c] = 0.f; }
+      if (i < cin && x0 + xs < hi) {
+        const unsigned *p = phib + (long long)i * 12 * V + Ps[xs];
+        float pr[12], pi[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const unsigned wv = p[(long long)c * V];
+          pr[c] = bf16_lo(wv);
+          pi[c] = bf16_hi(wv);
+        }
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              const float tr = Ts[xs][2 * (3 * a + b)], ti = Ts[xs][2 * (3 * a + b) + 1];
+              re += tr * pr[3 * sp + b] - ti * pi[3 * sp + b];
+              im += tr * pi[3 * sp + b] + ti * pr[3 * sp + b];
+            }
+            qr[3 * sp + a] = re;
+            qi[3 * sp + a] = -im;
+          }
+      }
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Bs[(3 * xs + a) * ldb + 4 * i + sp] = bf16_word(qr[3 * sp + a], qi[3 * sp + a]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPtcTiles; ++q) {
+      const int tile = w + 4 * q;
+      if (tile < ntiles) {                     // uniform per wave
+        const int rt = tile / nt, ct = tile - rt * nt;
+        const int crow = 8 * rt + ((lane & 15) >> 1), col = 16 * ct + (lane & 15);
+#pragma unroll 4
+        for (int st = 0; st < kPtcCols / 8; ++st) {
+          const int cj = 8 * st + 2 * kq;
+          const unsigned m0 = As[crow * lda + cj], m1 = As[crow * lda + cj + 1];
+          // Re row: (Mr, -Mi); Im row: (Mi, Mr)
+          const unsigned a0 = ri ? ((m0 >> 16) | (m0 << 16)) : (m0 ^ 0x80000000u);
+          const unsigned a1 = ri ? ((m1 >> 16) | (m1 << 16)) : (m1 ^ 0x80000000u);
+          const unsigned b0 = Bs[cj * ldb + col], b1 = Bs[(cj + 1) * ldb + col];
+          v4s_ptc av, bv;
+          av[0] = (short)(a0 & 0xffffu); av[1] = (short)(a0 >> 16); av[2] = (short)(a1 & 0xffffu); av[3] = (short)(a1 >> 16);
+          bv[0] = (short)(b0 & 0xffffu); bv[1] = (short)(b0 >> 16); bv[2] = (short)(b1 & 0xffffu); bv[3] = (short)(b1 >> 16);
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // acc[q][r] = D[4 kq + r][col]: complex row 8 rt + 2 kq + (r >> 1), Re/Im = r & 1
+  const long long nW = (long long)cout * cin * kPtcOffsets * 16;
+#pragma unroll
+  for (int q = 0; q < kPtcTiles; ++q) {
+    const int tile = w + 4 * q;
+    if (tile < ntiles) {
+      const int rt = tile / nt, ct = tile - rt * nt;
+      const int col = 16 * ct + (lane & 15), i = col >> 2, tc = col & 3;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int crow = 8 * rt + 2 * kq + h, o = crow >> 2, sp = crow & 3;
+        if (o < cout && i < cin)
+          part[ch * nW + (((long long)o * cin + i) * kPtcOffsets + k) * 16 + 4 * sp + tc] =
+              float2{acc[q][2 * h], acc[q][2 * h + 1]};
+      }
+    }
+  }
+}
+
+// gW[e] = sum over the chunks of part[chunk][e], in chunk order, in FP64
+__global__ void k_ptc_gw_sum(long long nW, int nchunk, const float2 *__restrict__ part, c128 *__restrict__ gW) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nW) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    const float2 v = part[c * nW + e];
+    re += v.x;
+    im += v.y;
+  }
+  gW[e] = c128{re, im};
 }
 
 }  // namespace
@@ -693,13 +851,73 @@ void launch_ptc_forward_bf16(const Geom &g, const c128 *U, int cin, const c128 *
   const int mrows = ((cout + 1) / 2) * 8, kcols = ((cin + 1) / 2) * 8;
   unsigned *Wb = scratch, *phib = scratch + (size_t)kPtcOffsets * mrows * kcols;
   const long long nw = (long long)kPtcOffsets * mrows * kcols, nf = (long long)cin * 12 * g.V;
-  hipLaunchKernelGGL(k_ptc_weights_bf16, dim3(blocks_for(nw, 256)), dim3(256), 0, st, W, cin, cout, mrows, kcols, Wb);
+  hipLaunchKernelGGL((k_ptc_weights_bf16<false>), dim3(blocks_for(nw, 256)), dim3(256), 0, st, W, cin, cout, mrows,
+                     kcols, Wb);
   LQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_fields_bf16, dim3(blocks_for(nf, 256)), dim3(256), 0, st, phi, nf, phib);
   LQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_ptc_forward_bf16, dim3(blocks_for(g.V, kPtcSites)), dim3(256), 0, st, g, U, cin, cout, mrows,
-                     kcols, phib, Wb, out);
+  hipLaunchKernelGGL((k_ptc_forward_bf16<false>), dim3(blocks_for(g.V, kPtcSites)), dim3(256), 0, st, g, U, cin, cout,
+                     mrows, kcols, phib, Wb, out);
   LQ_HIP(hipGetLastError());
+}
+
+namespace {
+struct PtcBwdPlan {
+  int mrows_in, kcols_in;                        // the adjoint product (input gradient)
+  int mrows_w, ncols_w, chunk, nchunk;           // the weight-gradient product
+  size_t off_phi, off_w, off_part, words;
+};
+
+PtcBwdPlan ptc_bwd_plan(int V, int cin, int cout) {
+  PtcBwdPlan p;
+  p.mrows_in = ((cin + 1) / 2) * 8;
+  p.kcols_in = ((cout + 1) / 2) * 8;
+  p.mrows_w = ((cout + 1) / 2) * 8;
+  p.ncols_w = ((cin + 3) / 4) * 16;
+  // chunks of about 2048 sites (at most 32), a multiple of the 32 sites of a step
+  const int want = std::max(1, std::min(32, (V + 2047) / 2048));
+  p.chunk = ((V + want - 1) / want + kPtcSites - 1) / kPtcSites * kPtcSites;
+  p.nchunk = (V + p.chunk - 1) / p.chunk;
+  const size_t nW = (size_t)cout * cin * kPtcOffsets * 16;
+  p.off_phi = (size_t)cout * 12 * V;
+  p.off_w = p.off_phi + (size_t)cin * 12 * V;
+  p.off_part = p.off_w + (size_t)kPtcOffsets * p.mrows_in * p.kcols_in;
+  p.off_part = (p.off_part + 1) & ~(size_t)1;     // float2 alignment
+  p.words = p.off_part + 2 * (size_t)p.nchunk * nW;
+  return p;
+}
+}  // namespace
+
+size_t ptc_bf16_backward_scratch_words(int V, int cin, int cout) { return ptc_bwd_plan(V, cin, cout).words; }
+
+void launch_ptc_backward_bf16(const Geom &g, const c128 *U, int cin, const c128 *phi, int cout, const c128 *W,
+                              const c128 *gout, c128 *gin, c128 *gW, unsigned *scratch, hipStream_t st) {
+  const PtcBwdPlan p = ptc_bwd_plan(g.V, cin, cout);
+  unsigned *gb = scratch, *phib = scratch + p.off_phi, *Wb = scratch + p.off_w;
+  float2 *part = reinterpret_cast<float2 *>(scratch + p.off_part);
+  const long long ng = (long long)cout * 12 * g.V;
+  hipLaunchKernelGGL(k_fields_bf16, dim3(blocks_for(ng, 256)), dim3(256), 0, st, gout, ng, gb);
+  LQ_HIP(hipGetLastError());
+  if (gin) {
+    // the adjoint product: rows (i, t) of the input channels, K (o, s) of the output channels
+    const long long nw = (long long)kPtcOffsets * p.mrows_in * p.kcols_in;
+    hipLaunchKernelGGL((k_ptc_weights_bf16<true>), dim3(blocks_for(nw, 256)), dim3(256), 0, st, W, cin, cout,
+                       p.mrows_in, p.kcols_in, Wb);
+    LQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_ptc_forward_bf16<true>), dim3(blocks_for(g.V, kPtcSites)), dim3(256), 0, st, g, U, cout,
+                       cin, p.mrows_in, p.kcols_in, gb, Wb, gin);
+    LQ_HIP(hipGetLastError());
+  }
+  if (gW) {
+    const long long nf = (long long)cin * 12 * g.V, nW = (long long)cout * cin * kPtcOffsets * 16;
+    hipLaunchKernelGGL(k_fields_bf16, dim3(blocks_for(nf, 256)), dim3(256), 0, st, phi, nf, phib);
+    LQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ptc_grad_weight_bf16, dim3(p.nchunk, kPtcOffsets), dim3(256), 0, st, g, U, cin, cout,
+                       p.mrows_w, p.ncols_w, p.chunk, phib, gb, part);
+    LQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ptc_gw_sum, dim3(blocks_for(nW, 256)), dim3(256), 0, st, nW, p.nchunk, part, gW);
+    LQ_HIP(hipGetLastError());
+  }
 }
 
 }  // namespace lq

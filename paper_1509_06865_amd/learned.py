@@ -91,10 +91,11 @@ def eigen_targets(ctx: Context, U, m0, agg, tv0, k: int, tol: float = 1e-6, para
     return V, info
 
 
-def train_step(ctx: Context, U, net: Network, phi0, targets, agg, lr: float):
-    """One step: forward, loss, backward, Adam.  Returns the loss before the update."""
+def train_step(ctx: Context, U, net: Network, phi0, targets, agg, lr: float, bf16: bool = False):
+    """One step: forward, loss, backward, Adam (bf16: the layers on the
+    bfloat16 matrix cores).  Returns the loss before the update."""
     net.step += 1
-    return ctx.lcnn_train_step(U, phi0, net.weights, net.biases, targets, agg, net.state, lr, net.step)
+    return ctx.lcnn_train_step(U, phi0, net.weights, net.biases, targets, agg, net.state, lr, net.step, bf16=bf16)
 
 
 def propose(ctx: Context, U, net: Network, phi0, bf16: bool = False):
@@ -121,17 +122,18 @@ def setup_and_solve(ctx: Context, U, m0, agg, tv0, params: MGParams, n_eig: int,
 
 
 def learned_solve(ctx: Context, U, m0, agg, net: Network, phi0, params_learned: MGParams, params_plain: MGParams,
-                  n_eig: int, tol: float, V0=None, nv: int | None = None):
+                  n_eig: int, tol: float, V0=None, nv: int | None = None, bf16: bool = False):
     """The learned setup with the plain one as fallback: the network's outputs
     (their first Nv) are the test vectors of a setup with params_learned; if
     the eigensolver then stops short of the tolerance (its residual stalled
     within the sweep limit), the plain setup from phi0 with params_plain is run
-    and the solve repeated.  Returns (lambda, V, resid, info) with info
+    and the solve repeated (bf16: the network's layers on the bfloat16 matrix
+    cores).  Returns (lambda, V, resid, info) with info
     extended by 'learned' (bool: the learned hierarchy gave the result),
     'setup_s', 'rqi_s', 'network_s' and, after a fallback, 'fallback_s'."""
     torch.cuda.synchronize()
     t0 = time.time()
-    X = propose(ctx, U, net, phi0)
+    X = propose(ctx, U, net, phi0, bf16=bf16)
     torch.cuda.synchronize()
     t_net = time.time() - t0
     nv = X.shape[0] if nv is None else nv

@@ -26,7 +26,7 @@ EXPORTED = ["lq_params_default", "lq_create", "lq_destroy", "lq_last_error", "q_
             "lq_kernel_timer_start", "lq_kernel_timer_read", "lq_herm_eigh", "lq_coarse_variant", "lq_ptc_forward", "lq_mod_relu", "lq_ptc_backward",
             "lq_mod_relu_backward", "lq_proj_loss", "lq_adam_step", "lq_inner_products_noalloc", "mg_info2",
             "mg_get_level2", "lma_low", "lma_high", "lq_timeslice_products", "lanczos_lowmodes",
-            "lq_clover", "lq_ptc_forward_bf16"]
+            "lq_clover", "lq_ptc_forward_bf16", "lq_ptc_backward_bf16"]
 
 # kernel classes of lq_kernel_timer_start
 KT_WILSON, KT_SAP, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_GRAM, KT_COMBINE = range(7)
@@ -154,6 +154,7 @@ def load():
         "lq_ptc_forward": (i, [vp, vp, i, vp, i, vp, vp]),
         "lq_mod_relu": (i, [vp, i, vp, vp, vp]),
         "lq_ptc_backward": (i, [vp, vp, i, vp, i, vp, vp, vp, vp]),
+        "lq_ptc_backward_bf16": (i, [vp, vp, i, vp, i, vp, vp, vp, vp]),
         "lq_mod_relu_backward": (i, [vp, i, vp, vp, vp, vp, vp]),
         "lq_proj_loss": (i, [vp, ip, i, vp, i, vp, dp, vp]),
         "lq_adam_step": (i, [vp, C.c_longlong, vp, vp, vp, vp, d, d, d, d, i]),
@@ -276,6 +277,19 @@ class Context:
                                              _ptr(g_out.contiguous()), _ptr(g_in), _ptr(g_W)))
         return g_in, g_W
 
+    def ptc_backward_bf16(self, U: torch.Tensor, phi: torch.Tensor, W: torch.Tensor, g_out: torch.Tensor,
+                          need_in: bool = True, need_W: bool = True):
+        """The same gradients on the bfloat16 matrix cores (FP32 accumulation),
+        c_in, c_out <= 24; a gradient not asked for is returned as None."""
+        c_in, c_out = int(phi.shape[0]), int(W.shape[0])
+        self._net_args(U, phi, W, c_in, c_out)
+        _need(g_out, "g_out", (c_out, 12, self.V), torch.complex128)
+        g_in = torch.empty_like(phi) if need_in else None
+        g_W = torch.empty_like(W) if need_W else None
+        self._check(self.lib.lq_ptc_backward_bf16(self.h, _ptr(U), c_in, _ptr(phi), c_out, _ptr(W.contiguous()),
+                                                  _ptr(g_out.contiguous()), _ptr(g_in), _ptr(g_W)))
+        return g_in, g_W
+
     def _net_args(self, U, phi, W, c_in, c_out):
         _need(U, "U", (4, 9, self.V), torch.complex128)
         _need(phi, "phi", (c_in, 12, self.V), torch.complex128)
@@ -303,30 +317,33 @@ class Context:
                                                   _ptr(g_out.contiguous()), _ptr(g_phi), _ptr(g_b)))
         return g_phi, g_b
 
-    def _forward_keep(self, U, phi0, weights, biases):
+    def _forward_keep(self, U, phi0, weights, biases, bf16=False):
         inputs, pre = [], []
         phi = phi0
+        layer_fn = self.ptc_forward_bf16 if bf16 else self.ptc_forward
         for layer, W in enumerate(weights):
             inputs.append(phi)
-            phi = self.ptc_forward(U, phi, W)
+            phi = layer_fn(U, phi, W)
             if layer < len(weights) - 1:
                 pre.append(phi)
                 phi = self.mod_relu(phi, biases[layer])
         return phi, inputs, pre
 
     def lcnn_backward(self, U: torch.Tensor, phi0: torch.Tensor, weights, biases, g_out: torch.Tensor,
-                      kept=None):
+                      kept=None, bf16: bool = False):
         """Gradients of a real loss with respect to every weight and bias of the
         network, given g_out for its output: the forward is rerun (or its kept
         intermediates used) to have each layer's input, then the library's
-        backward calls run in reverse order."""
-        _, inputs, pre = kept if kept is not None else self._forward_keep(U, phi0, weights, biases)
+        backward calls run in reverse order (the layers' on the bfloat16
+        matrix cores with bf16)."""
+        _, inputs, pre = kept if kept is not None else self._forward_keep(U, phi0, weights, biases, bf16)
+        layer_bwd = self.ptc_backward_bf16 if bf16 else self.ptc_backward
         g = g_out
         gW, gb = [None] * len(weights), [None] * len(biases)
         for layer in range(len(weights) - 1, -1, -1):
             if layer < len(weights) - 1:
                 g, gb[layer] = self.mod_relu_backward(pre[layer], biases[layer], g)
-            g, gW[layer] = self.ptc_backward(U, inputs[layer], weights[layer], g)
+            g, gW[layer] = layer_bwd(U, inputs[layer], weights[layer], g)
         return gW, gb
 
     def proj_loss(self, X: torch.Tensor, u: torch.Tensor, agg, grad: bool = True):
@@ -354,14 +371,16 @@ class Context:
         self._check(self.lib.lq_adam_step(self.h, pr.numel(), _ptr(pr), _ptr(gr.contiguous()), _ptr(m), _ptr(v),
                                           float(lr), float(betas[0]), float(betas[1]), float(eps), int(t)))
 
-    def lcnn_train_step(self, U, phi0, weights, biases, u, agg, state, lr, t):
+    def lcnn_train_step(self, U, phi0, weights, biases, u, agg, state, lr, t, bf16: bool = False):
         """One training step of the network on the device: forward, loss over
         the aggregates, backward, Adam (step t) on every weight and bias in
         place.  state: the Adam moments, a list of (m, v) per parameter
-        (weights then biases).  Returns the loss before the update."""
-        out, inputs, pre = self._forward_keep(U, phi0, weights, biases)
+        (weights then biases).  bf16: the layers' forward and backward on the
+        bfloat16 matrix cores (weights, moments and the update stay FP64).
+        Returns the loss before the update."""
+        out, inputs, pre = self._forward_keep(U, phi0, weights, biases, bf16)
         loss, gX = self.proj_loss(out, u, agg)
-        gW, gb = self.lcnn_backward(U, phi0, weights, biases, gX, kept=(out, inputs, pre))
+        gW, gb = self.lcnn_backward(U, phi0, weights, biases, gX, kept=(out, inputs, pre), bf16=bf16)
         for p, g, (m, v) in zip(list(weights) + list(biases), gW + gb, state):
             self.adam_step(p, g, m, v, lr, t=t)
         return loss

@@ -224,6 +224,86 @@ def test_ptc_layer_gradients_match_oracle_autograd(t_bc):
     assert relmax(host(d_W), gW.numpy()) < 1e-12
 
 
+@pytest.mark.parametrize("t_bc", [-1, 1])
+def test_ptc_layer_bf16_gradients_match_oracle_autograd(t_bc):
+    # the layer's gradients on the bfloat16 matrix cores against the oracle's
+    # autograd, at the bfloat16 bar (norm-relative <= 3e-2, cosine >= 0.999),
+    # with the rounding visibly present; 120 sites: a ragged step of 32 sites
+    from oracle import lcnn
+    dims = (6, 2, 2, 5)
+    lat = Lattice(dims, t_bc)
+    U = lqsynth.gauge_field(dims, 0.4, 121)
+    phi = lqsynth.gaussian_spinors(3, dims, 122)
+    rng = np.random.default_rng(123)
+    W = (rng.standard_normal((5, 3, 81, 4, 4)) + 1j * rng.standard_normal((5, 3, 81, 4, 4))) / 30
+    G = lqsynth.gaussian_spinors(5, dims, 124)
+    phi_t = torch.from_numpy(phi).requires_grad_(True)
+    W_t = torch.from_numpy(W).requires_grad_(True)
+    out = lcnn.forward(lcnn.transports(U, lat), phi_t, [W_t], [])
+    L = torch.real((torch.from_numpy(G).conj() * out).sum())
+    gphi, gW = torch.autograd.grad(L, [phi_t, W_t])
+    c = _ctx(dims, t_bc)
+    d_in, d_W = c.ptc_backward_bf16(dev(U), dev(phi), dev(W), dev(G))
+    for got, ref in ((host(d_in), gphi.numpy()), (host(d_W), gW.numpy())):
+        cos, rel = _cos_rel(got, ref)
+        assert rel <= 3e-2 and cos >= 0.999, (rel, cos)
+        assert rel > 1e-5
+    # each output alone (the other pointer NULL) gives the same values
+    d_in2, none_W = c.ptc_backward_bf16(dev(U), dev(phi), dev(W), dev(G), need_W=False)
+    none_in, d_W2 = c.ptc_backward_bf16(dev(U), dev(phi), dev(W), dev(G), need_in=False)
+    assert none_W is None and none_in is None
+    assert np.array_equal(host(d_in2), host(d_in)) and np.array_equal(host(d_W2), host(d_W))
+
+
+@pytest.mark.parametrize("dims,cin,cout", [((8, 8, 8, 8), 16, 16), ((8, 8, 8, 8), 24, 16),
+                                           ((8, 8, 8, 8), 16, 24), ((6, 6, 6, 14), 7, 9),
+                                           ((16, 16, 16, 16), 16, 16)])
+def test_ptc_layer_bf16_gradients_at_network_widths(dims, cin, cout):
+    # the network's widths and an odd pair against the direct FP64 gradients
+    # (themselves equal to the oracle's autograd to 1e-12); 6^3 x 14 splits
+    # its 3024 sites into two chunks with a ragged last step, 16^4 into 32
+    print(f"[ptc bf16 grad] {cin} -> {cout} on {dims}", flush=True)
+    U = dev(lqsynth.gauge_field(dims, 0.3, 125))
+    phi = dev(lqsynth.gaussian_spinors(cin, dims, 126))
+    G = dev(lqsynth.gaussian_spinors(cout, dims, 127))
+    rng = np.random.default_rng(128)
+    W = dev((rng.standard_normal((cout, cin, 81, 4, 4)) + 1j * rng.standard_normal((cout, cin, 81, 4, 4))) / 60)
+    c = _ctx(dims, 1)
+    r_in, r_W = c.ptc_backward(U, phi, W, G)
+    d_in, d_W = c.ptc_backward_bf16(U, phi, W, G)
+    for got, ref in ((d_in, r_in), (d_W, r_W)):
+        cos, rel = _cos_rel(host(got), host(ref))
+        assert rel <= 3e-2 and cos >= 0.999, (rel, cos)
+
+
+def test_learned_setup_network_bf16_gradients_match_oracle_autograd():
+    # backpropagation through the network with every layer's forward and
+    # backward on the bfloat16 matrix cores, against the oracle's autograd:
+    # each weight and bias gradient at the bfloat16 bar
+    from oracle import lcnn
+    dims = (4, 2, 4, 6)
+    lat = Lattice(dims, -1)
+    U = lqsynth.gauge_field(dims, 0.4, 131)
+    phi = lqsynth.gaussian_spinors(3, dims, 132)
+    rng = np.random.default_rng(133)
+    chans = (3, 4, 4, 2)
+    Ws = [(rng.standard_normal((co, ci, 81, 4, 4)) + 1j * rng.standard_normal((co, ci, 81, 4, 4))) / (10 * ci)
+          for ci, co in zip(chans[:-1], chans[1:])]
+    bs = [-0.2 * rng.random(co) for co in chans[1:-1]]
+    G = lqsynth.gaussian_spinors(2, dims, 134)
+    Wt = [torch.from_numpy(w).requires_grad_(True) for w in Ws]
+    bt = [torch.from_numpy(b).requires_grad_(True) for b in bs]
+    out = lcnn.forward(lcnn.transports(U, lat), torch.from_numpy(phi), Wt, bt)
+    L = torch.real((torch.from_numpy(G).conj() * out).sum())
+    grads = torch.autograd.grad(L, Wt + bt)
+    c = _ctx(dims, -1)
+    gW, gb = c.lcnn_backward(dev(U), dev(phi), [dev(w) for w in Ws], [torch.from_numpy(b).cuda() for b in bs],
+                             dev(G), bf16=True)
+    for got, ref in zip([host(w) for w in gW] + [b.cpu().numpy() for b in gb], [g.numpy() for g in grads]):
+        cos, rel = _cos_rel(got, ref)
+        assert rel <= 3e-2 and cos >= 0.999, (rel, cos)
+
+
 def test_learned_setup_network_gradients_match_oracle_autograd():
     # backpropagation through three layers and two nonlinearities on the
     # device (the library's backward calls in reverse order) against autograd
@@ -272,9 +352,12 @@ def test_learned_setup_loss_and_gradient_match_oracle():
     assert relmax(host(gX), gX_ref.numpy()) < 1e-10
 
 
-def test_learned_setup_training_steps_match_oracle():
+@pytest.mark.parametrize("bf16", [False, True], ids=["fp64", "bf16"])
+def test_learned_setup_training_steps_match_oracle(bf16):
     # two training steps on the device (forward, loss, backward, Adam) against
     # the oracle's network trained by torch's Adam: losses and updated weights
+    # (with the bfloat16 layers: losses to 3e-2 and the updates in the same
+    # direction, Adam's first steps being nearly the gradients' signs)
     from oracle import lcnn
     dims, agg = (4, 2, 4, 6), (2, 2, 2, 2)
     lat = Lattice(dims, -1)
@@ -307,12 +390,16 @@ def test_learned_setup_training_steps_match_oracle():
     for p in dW + db:
         pr = torch.view_as_real(p) if p.is_complex() else p
         state.append((torch.zeros_like(pr), torch.zeros_like(pr)))
-    losses = [c.lcnn_train_step(dev(U), dev(phi), dW, db, dev(u), agg, state, 1e-2, t) for t in (1, 2)]
+    losses = [c.lcnn_train_step(dev(U), dev(phi), dW, db, dev(u), agg, state, 1e-2, t, bf16=bf16) for t in (1, 2)]
     for a, b in zip(losses, ref_losses):
-        assert abs(a - b) <= 1e-12 * abs(b)
-    for p_dev, p_ref in zip(dW + db, params):
+        assert abs(a - b) <= (3e-2 if bf16 else 1e-12) * abs(b), (a, b)
+    for p_dev, p_ref, p0 in zip(dW + db, params, Ws + bs):
         ref = p_ref.detach().numpy()
-        assert np.abs(p_dev.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+        if bf16:
+            cos, _ = _cos_rel(p_dev.cpu().numpy() - p0, ref - p0)
+            assert cos >= 0.9, cos
+        else:
+            assert np.abs(p_dev.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
 def test_learned_setup_network_forward_matches_oracle():

@@ -388,7 +388,8 @@ def test_rqi_three_levels_returns_exactly_the_lowest_cluster():
 
 
 # ------------------------------------------------ learned setup: the gain ---
-def test_learned_setup_training_gains_over_the_untrained_start():
+@pytest.mark.parametrize("bf16", [False, True], ids=["fp64", "bf16"])
+def test_learned_setup_training_gains_over_the_untrained_start(bf16):
     # A 2-layer network (8 -> 8 -> 8 channels) trained for 40 steps on one
     # 8^4 field to represent its 8 lowest eigenvectors (per-aggregate
     # projection loss), then applied to another field of the same ensemble:
@@ -401,7 +402,7 @@ def test_learned_setup_training_gains_over_the_untrained_start():
     dims, agg, K = DIMS8, AGG4, 8
     V = int(np.prod(dims))
     m0 = -0.2
-    print("[learned gain] 8^4, 8 -> 8 -> 8, 40 steps", flush=True)
+    print(f"[learned gain] 8^4, 8 -> 8 -> 8, 40 steps, bf16 layers {bf16}", flush=True)
     c = _ctx(dims, 1)
     tprm = MGParams(precision=1, rqi_block=16, n_setup=3, coarse_m=40, coarse_tol=0.1, rqi_guard=8,
                     rayleigh_ritz=1, rqi_max_sweeps=30)
@@ -410,14 +411,14 @@ def test_learned_setup_training_gains_over_the_untrained_start():
     tgt, info = L.eigen_targets(c, Utr, m0, agg, phi_tr, K, 1e-8, tprm)
     assert info["converged"], info
     net = L.init_network(channels=(8, 8, 8), seed=183, scale=0.3)
-    losses = [L.train_step(c, Utr, net, phi_tr, tgt, agg, 2e-2) for _ in range(40)]
+    losses = [L.train_step(c, Utr, net, phi_tr, tgt, agg, 2e-2, bf16=bf16) for _ in range(40)]
     assert losses[-1] < 0.8 * losses[0], losses[::8]
     # held-out field
     Ute = dev(lqsynth.gauge_field(dims, 0.3, 191))
     phi_te = L.gaussian_fields(K, V, 192)
     ref, info = L.eigen_targets(c, Ute, m0, agg, phi_te, K, 1e-8, tprm)
     assert info["converged"], info
-    X = L.propose(c, Ute, net, phi_te)
+    X = L.propose(c, Ute, net, phi_te, bf16=bf16)
     loss_net = L.loss_of(c, X, ref, agg)
     loss_rand = L.loss_of(c, phi_te, ref, agg)
     print("held-out loss: network", loss_net, "random", loss_rand, flush=True)
