@@ -25,16 +25,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time for lowest-100 eigenpairs of Q at 32^3x64, tol 1e-10; Dirac-apply HBM GB/s"
 DEFAULT_CLASS = "sap"          # the kernel class with the largest share of the step's device time
-# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE passes (scaled by a
-# plain copy of known size), by kernel class and workload, with the SHA-256 of
-# the kernel's source at the time; reported only while the source is unchanged
+# HBM bytes per launch from rocprofv3 counter passes: reads from the L2's read
+# requests by size (TCC_EA0_RDREQ_128B x 128 + TCC_EA0_RDREQ_64B x 64; the
+# derived FETCH_SIZE counts every request as 64 B on this chip, half of what a
+# plain copy of known size reads), writes from WRITE_SIZE (equal to the copy's
+# written bytes), by kernel class and workload, with the SHA-256 of the kernel's
+# source at the time; reported only while the source is unchanged
 TRAFFIC = {
     # profiles/hbm_traffic_16x4.md: k_sap_colour<float, false>, one colour, 16 right-hand sides
-    # (source since changed only in the FP64 instantiation's register cap; the FP32 code is identical)
-    ("sap", "medium"): {"bytes_per_launch": 312.02e6,
+    ("sap", "medium"): {"bytes_per_launch": 537.80e6,
                         "source_sha256": "ca9ccebdcf4b8bc964eeae88d8748d398ba0fe6dedc88b95f79ad98973007c2d"},
     # k_coarse_apply_mfma (the tuned kernel), 16 right-hand sides, 256 coarse sites of 40 unknowns
-    ("coarse", "medium"): {"bytes_per_launch": 15.70e6,
+    ("coarse", "medium"): {"bytes_per_launch": 30.07e6,
                            "source_sha256": "2f797ceab98415869eb162ea6a2980e5d59e3dd56b6cc8ee92480f287417b69a"},
 }
 KSOURCES = {"wilson": ["wilson.hip", "lq_dslash.h"], "sap": ["sap.hip", "lq_dslash.h"],

@@ -57,9 +57,10 @@ def test_q_apply_with_clover_matches_oracle(dims, bc):
 
 
 def test_q_apply_with_clover_column_kernel():
-    # a lattice large enough for the timeslice-column kernel (one field, canonical)
+    # a lattice large enough for the timeslice-column kernel (one field,
+    # canonical): 32 x 32 x 16 spatial sites, four columns of 4 timeslices
     from paper_1509_06865_amd import Context
-    dims = (16, 16, 16, 8)
+    dims = (32, 32, 16, 16)
     print(f"[clover q_apply column kernel] {dims}", flush=True)
     U = lqsynth.gauge_field(dims, 0.4, 23)
     x = lqsynth.gaussian_spinors(1, dims, 24)

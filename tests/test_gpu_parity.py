@@ -54,7 +54,7 @@ def test_q_apply_fp64_matches_oracle(dims, bc):
     y = host(c.q_apply(dev(U), -0.2, dev(x)))
     torch.cuda.synchronize()
     assert relmax(y, ref) < 1e-13
-    # one field: the timeslice-column kernel (partial columns when T % 8 != 0)
+    # one field: the single-field kernel
     y1 = host(c.q_apply(dev(U), -0.2, dev(x[:1])))
     assert relmax(y1, ref[:1]) < 1e-13
 
@@ -82,11 +82,12 @@ def test_q_apply_many_rhs_chunks():
 
 
 def test_q_apply_timeslice_columns_partial_chunk_antiperiodic():
-    # 32^3 x 12, t antiperiodic, one field: the timeslice-column kernel with a
-    # partial last column (8 + 4 timeslices); sampled sites on both sides of
-    # the column boundary and of the t boundary, against the oracle.
+    # 32^3 x 13, t antiperiodic, one field: the timeslice-column kernel with
+    # two columns per spatial site, the second one shorter (7 + 6 timeslices);
+    # sampled sites on both sides of the column boundary and of the t
+    # boundary, against the oracle.
     from oracle.dirac import apply_Q_sites
-    dims = (32, 32, 32, 12)
+    dims = (32, 32, 32, 13)
     U = lqsynth.gauge_field(dims, 0.25, 61)
     lat = Lattice(dims, -1)
     x = lqsynth.gaussian_spinors(1, dims, 62)
@@ -97,7 +98,7 @@ def test_q_apply_timeslice_columns_partial_chunk_antiperiodic():
     S3 = 32 ** 3
     rng = np.random.default_rng(63)
     sp = rng.integers(0, S3, 12)
-    sites = np.concatenate([sp + S3 * t for t in (0, 7, 8, 11)] + [[0, S3 - 1, 12 * S3 - 1]])
+    sites = np.concatenate([sp + S3 * t for t in (0, 6, 7, 12)] + [[0, S3 - 1, 13 * S3 - 1]])
     ref = apply_Q_sites(U, -0.1, x[0], lat, sites)
     assert relmax(y64[:, sites], ref) < 1e-13
     assert relmax(y32[:, sites], ref) < 2e-6
