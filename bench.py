@@ -387,6 +387,11 @@ def learned_setup(args):
         log(f"field {j + 1}/{n_fields}: eps {eps:.3f} m0 {m0:.4f} targets converged {info['converged']} "
             f"({info['sweeps']} sweeps), loss {losses[-args.train_steps]:.4f} -> {losses[-1]:.4f}")
         del U, phi0, tgt
+    if args.learned_eval == "large":
+        ctx.close()                                 # the 16^4 context's buffers go back first
+        del ctx
+        learned_eval_large(args, net, L, losses, t_targets, t_train, n_fields)
+        return
     # evaluation on the benchmark field
     gold = load_golden("medium")
     m0 = gold["m0"]
@@ -443,6 +448,55 @@ def learned_setup(args):
         del Vv
     out["solve"] = res
     out["workload"] = f"16^4 eps={gold['eps']} m0={m0}, Nv={nv}, lowest {n_eig} at {wl['tol']}"
+    print(json.dumps(out), flush=True)
+
+
+def learned_eval_large(args, net, L, losses, t_targets, t_train, n_fields):
+    """The network trained on 16^4 fields applied to the 32^3 x 64 field: its
+    24 outputs against 24 random vectors as the test vectors of the large
+    workload's setup (the learned one with --learned-n-setup passes and no
+    initial ones), then the same capped number of eigensolver sweeps from the
+    same start vectors; pairs converged, residuals, times.  Prints one JSON line."""
+    import torch
+    import lqsynth
+    from paper_1509_06865_amd import Context, MGParams
+    torch.cuda.empty_cache()
+    gold = load_golden("large")
+    wl = WORKLOADS["large"]
+    dims, m0, agg = tuple(gold["dims"]), gold["m0"], wl["agg"]
+    nv, n_eig, guard = 24, wl["n_eig"], wl["guard"]
+    U = torch.from_numpy(lqsynth.gauge_field(dims, gold["eps"], gold["field_seed"])).cuda()
+    ctx = Context(dims, gold["t_bc"])
+    phi0 = device_gaussian(nv, dims, gold["field_seed"] + 1, torch)
+    V0 = device_gaussian(n_eig + guard - nv, dims, gold["field_seed"] + 2, torch)
+    base = dict(wl["params"], precision=1, rqi_guard=guard, rayleigh_ritz=1, rqi_max_sweeps=args.max_sweeps)
+    plain = MGParams(**base)
+    learned = MGParams(**dict(base, n_setup=args.learned_n_setup, n_init=0))
+    torch.cuda.synchronize()
+    a = time.time()
+    X = L.propose(ctx, U, net, phi0, bf16=args.train_bf16)
+    torch.cuda.synchronize()
+    t_net = time.time() - a
+    torch.cuda.empty_cache()                        # the layers' activations: back to the device for the solver
+    log(f"network on 32^3x64: {t_net:.2f} s")
+    out = {"train": {"fields": n_fields, "steps_per_field": args.train_steps, "lr": args.train_lr,
+                     "layers": "bf16_mfma" if args.train_bf16 else "fp64_direct",
+                     "first_loss": losses[0], "last_loss": losses[-1],
+                     "targets_s": round(t_targets, 1), "train_s": round(t_train, 1)},
+           "network_s": round(t_net, 3)}
+    res = {}
+    for name, tv, prm in (("plain", phi0, plain), ("learned", X, learned)):
+        lam, Vv, r, info, ts, tr = L.setup_and_solve(ctx, U, m0, agg, tv[:nv].contiguous(), prm, n_eig, wl["tol"],
+                                                     V0)
+        r = np.asarray(r, dtype=float)
+        res[name] = {"converged_pairs": int((r <= wl["tol"]).sum()), "sweeps": info["sweeps"],
+                     "solves": info["solves"], "fgmres_iters": info["fgmres_iters"], "setup_s": round(ts, 2),
+                     "rqi_s": round(tr, 2), "max_residual": float(r.max()), "median_residual": float(np.median(r))}
+        log(f"{name}: {res[name]}")
+        del Vv
+    out["solve"] = res
+    out["workload"] = (f"32^3x64 eps={gold['eps']} m0={m0}, Nv={nv}, lowest {n_eig} at {wl['tol']}, "
+                       f"at most {args.max_sweeps} sweeps")
     print(json.dumps(out), flush=True)
 
 
@@ -650,6 +704,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=1)
     ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--learned-n-setup", type=int, default=1)
+    ap.add_argument("--learned-eval", default="medium", choices=["medium", "large"],
+                    help="field the trained network is evaluated on: the 16^4 benchmark field, or 32^3 x 64 with "
+                         "--max-sweeps sweeps for both setups")
     ap.add_argument("--train-bf16", action="store_true",
                     help="train (and propose the learned setup's vectors) with the layers on the bfloat16 matrix cores")
     ap.add_argument("--lma", action="store_true", help="approximate low-mode averaging on the 16^4 field")

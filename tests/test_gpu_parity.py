@@ -700,7 +700,8 @@ def test_coarse_graph_replay_equals_direct_launches(prec):
 # FGMRES does not converge there (the oracle needs > 400 steps at sigma = 0.49),
 # with Nv = 16 it takes ~20.  That case therefore runs with 16 test vectors.
 @pytest.mark.parametrize("name,prec,nv,bf16", [("tiny_periodic", 0, 8, 0), ("tiny_periodic", 1, 8, 0),
-                                               ("tiny_antiperiodic", 1, 16, 0), ("tiny_periodic", 1, 8, 1)])
+                                               ("tiny_antiperiodic", 0, 16, 0), ("tiny_antiperiodic", 1, 16, 0),
+                                               ("tiny_periodic", 1, 8, 1)])
 def test_rqi_lowest_eight_match_dense(name, prec, nv, bf16):
     dims, bc, eps, seed, m0 = tiny(name)
     U = lqsynth.gauge_field(dims, eps, seed)
