@@ -78,9 +78,10 @@ WORKLOADS = {
     "large": dict(golden="large", agg=(4, 4, 4, 4), nv=32, n_eig=100, tol=1e-10, guard=32,
                   params=dict(rqi_block=8, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
                               coarse_tol=0.15, rqi_start_passes=6, rqi_solve_restarts=0)),
+    # medium: FGMRES(7) and 8 start passes measured fastest in a sweep of the solver parameters
     "medium": dict(golden="medium", agg=(4, 4, 4, 4), nv=20, n_eig=50, tol=1e-10, guard=70,
-                   params=dict(rqi_block=16, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
-                               coarse_tol=0.3, rqi_start_passes=6, rqi_solve_restarts=0)),
+                   params=dict(rqi_block=16, fgmres_m=7, n_setup=4, coarse_m=40, coarse_restarts=1,
+                               coarse_tol=0.3, rqi_start_passes=8, rqi_solve_restarts=0)),
     "small": dict(golden="tiny_periodic", agg=(2, 2, 2, 2), nv=8, n_eig=8, tol=1e-10, guard=4,
                   params=dict(rqi_block=4, fgmres_m=10, n_setup=4, coarse_m=128, coarse_restarts=2,
                               coarse_tol=1e-8)),

@@ -797,7 +797,8 @@ def test_rqi_exactly_degenerate_free_field_shell(prec):
 
 def test_rqi_benchmark_workload_returns_exact_pairs():
     # The benchmark's configuration at full size (16^4, 50 lowest pairs,
-    # Nv = 20, guard 70, 6 start passes, blocks of 16 shifted solves): every
+    # Nv = 20, guard 70, 8 start passes, blocks of 16 shifted solves of one
+    # FGMRES(7) cycle): every
     # returned pair is an eigenpair of the oracle's Q to the tolerance,
     # lambda is its Rayleigh quotient, the vectors are orthonormal and sorted
     # by |lambda|.  (A dense reference is out of reach at 786k unknowns.)
@@ -808,8 +809,8 @@ def test_rqi_benchmark_workload_returns_exact_pairs():
     from paper_1509_06865_amd import MGParams
     c = _ctx(dims, bc)
     c.mg_setup(dev(U), m0, (4, 4, 4, 4), dev(lqsynth.gaussian_spinors(20, dims, 202)),
-               MGParams(precision=1, rqi_block=16, fgmres_m=8, n_setup=4, coarse_m=40, coarse_restarts=1,
-                        coarse_tol=0.3, rqi_start_passes=6, rqi_solve_restarts=0, rqi_guard=70, rayleigh_ritz=1,
+               MGParams(precision=1, rqi_block=16, fgmres_m=7, n_setup=4, coarse_m=40, coarse_restarts=1,
+                        coarse_tol=0.3, rqi_start_passes=8, rqi_solve_restarts=0, rqi_guard=70, rayleigh_ritz=1,
                         rqi_max_sweeps=20))
     V0 = dev(lqsynth.gaussian_spinors(50 + 70 - 20, dims, 203))
     lam, V, res, info = c.rqi_lowmodes(50, 1e-10, V0=V0)
