@@ -690,6 +690,8 @@ def main():
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the all-FP64 comparison solve")
+    ap.add_argument("--no-large-solve", action="store_true",
+                    help="skip the 20-pair solve on the 32^3 x 64 lattice after the timed step")
     ap.add_argument("--n-eig", type=int, default=None, help="override the workload's eigenpair count")
     ap.add_argument("--guard", type=int, default=None)
     ap.add_argument("--nv", type=int, default=None)
@@ -902,7 +904,34 @@ def main():
                                                          "fp32": round(480.0 * bV / b32 / 1e9, 1),
                                                          "fp64_ms": round(b64 * 1e3, 4), "fp32_ms": round(b32 * 1e3, 4)}
         log(f"q_apply at 32^3x64: FP64 {b64 * 1e3:.3f} ms, FP32 {b32 * 1e3:.3f} ms")
-        del bU, bx, bctx
+        del bx
+        if not args.no_large_solve:
+            # time to solution on the same lattice for the 20 lowest pairs (the eigenpair count of
+            # the paper's comparisons; guard 20 covers the momentum shell the 20th mode lies in),
+            # the large workload's solver parameters
+            lw = WORKLOADS["large"]
+            ne, gd = 20, 20
+            tv0_l = device_gaussian(lw["nv"], bdims, big["field_seed"] + 1, torch)
+            V0_l = device_gaussian(ne + gd - lw["nv"], bdims, big["field_seed"] + 2, torch)
+            prm_l = MGParams(precision=1, rqi_guard=gd, rayleigh_ritz=1, rqi_max_sweeps=30, **lw["params"])
+            torch.cuda.empty_cache()
+            torch.cuda.synchronize()
+            a = time.time()
+            bctx.mg_setup(bU, big["m0"], lw["agg"], tv0_l, prm_l)
+            torch.cuda.synchronize()
+            t_set = time.time() - a
+            lam_l, V_l, res_l, info_l = bctx.rqi_lowmodes(ne, lw["tol"], V0=V0_l)
+            torch.cuda.synchronize()
+            t_l = time.time() - a
+            out["config"]["lowest20_32x32x32x64"] = {
+                "s": round(t_l, 3), "setup_s": round(t_set, 3), "converged": bool(info_l["converged"]),
+                "sweeps": info_l["sweeps"], "solves": info_l["solves"], "fgmres_iters": info_l["fgmres_iters"],
+                "max_residual": float(max(res_l)), "smallest_abs_lambda": float(min(abs(v) for v in lam_l)),
+                "largest_abs_lambda": float(max(abs(v) for v in lam_l)), "nv": lw["nv"], "guard": gd}
+            log(f"32^3x64, 20 lowest at {lw['tol']}: {t_l:.2f} s (setup {t_set:.2f} s), converged "
+                f"{info_l['converged']}, sweeps {info_l['sweeps']}")
+            del tv0_l, V0_l, V_l
+        del bU, bctx
     else:
         out["config"]["dirac_apply_gbs_32x32x32x64"] = out["config"]["dirac_apply_gbs"]
     gpu_tiny = None
