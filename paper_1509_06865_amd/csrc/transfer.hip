@@ -11,12 +11,6 @@
 namespace lq {
 namespace {
 
-__device__ inline double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // Wave sum of N values per lane (N a power of two, at most 64) by a transposed
 // butterfly: at offset o each lane keeps half of its values, hands the other
 // half to lane ^ o and adds what it receives, so N values cost N - 1 shuffles
@@ -155,6 +149,7 @@ template <typename T> constexpr int transfer_group() { return sizeof(T) == 4 ? 4
 // diagonal), the workgroup writes nothing, so that block of P keeps its
 // previous columns, and raises *status.
 constexpr int kMaxNv = 32;
+constexpr int kGramBatch = 8;                    // Gram entries whose wave sums run interleaved
 __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *const *__restrict__ cols, int Nv,
                                                  c128 *__restrict__ P, int *status) {
   __shared__ double part[4][kMaxNv * (kMaxNv + 1) / 2 * 2];   // wave partial sums of the Gram entries
@@ -169,28 +164,51 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *const *__re
   for (int pass = 0; pass < 2; ++pass) {
     // field k of this pass: test vector k (its own address), then column k of P
     auto field = [&](int k) -> const c128 * { return (pass == 0) ? cols[k] : P + (long long)k * 12 * g.V; };
-    // Gram partials, pairs (i <= j) in row-major order
-    int pidx = 0;
+    // Gram partials, pairs (i <= j) in row-major order; the wave sums of
+    // kGramBatch entries at a time run interleaved
+    int pbase = 0;
+#pragma unroll 1
     for (int i = 0; i < Nv; ++i) {
       c128 wi[6];
       const c128 *fi = field(i);
 #pragma unroll
       for (int r = 0; r < 6; ++r)
         wi[r] = active ? fi[(long long)(6 * h + r) * g.V + s] : c128{0, 0};
-      for (int jj = i; jj < Nv; ++jj, ++pidx) {
-        double re = 0, im = 0;
-        if (active) {
-          const c128 *fj = field(jj);
+#pragma unroll 1
+      for (int j0 = i; j0 < Nv; j0 += kGramBatch) {
+        double re[kGramBatch], im[kGramBatch];
 #pragma unroll
-          for (int r = 0; r < 6; ++r) {
-            const c128 wj = fj[(long long)(6 * h + r) * g.V + s];
-            re += wi[r].re * wj.re + wi[r].im * wj.im;
-            im += wi[r].re * wj.im - wi[r].im * wj.re;
+        for (int b = 0; b < kGramBatch; ++b) {
+          re[b] = 0;
+          im[b] = 0;
+          if (active && j0 + b < Nv) {
+            const c128 *fj = field(j0 + b);
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+              const c128 wj = fj[(long long)(6 * h + r) * g.V + s];
+              re[b] += wi[r].re * wj.re + wi[r].im * wj.im;
+              im[b] += wi[r].re * wj.im - wi[r].im * wj.re;
+            }
           }
         }
-        re = wsum(re); im = wsum(im);
-        if (lane == 0) { part[wave][2 * pidx] = re; part[wave][2 * pidx + 1] = im; }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+          for (int b = 0; b < kGramBatch; ++b) {
+            re[b] += __shfl_xor(re[b], off, 64);
+            im[b] += __shfl_xor(im[b], off, 64);
+          }
+        if (lane == 0) {
+#pragma unroll
+          for (int b = 0; b < kGramBatch; ++b)
+            if (j0 + b < Nv) {
+              const int q = pbase + j0 + b - i;
+              part[wave][2 * q] = re[b];
+              part[wave][2 * q + 1] = im[b];
+            }
+        }
       }
+      pbase += Nv - i;
     }
     __syncthreads();
     // Gram matrix into L (upper part, then Cholesky in place by thread 0)
@@ -224,13 +242,24 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *const *__re
     // P rows: p = w L^-dag  <=>  sum_{i<=j} p_i conj(L[j][i]) = w_j
     if (active) {
       for (int r = 0; r < 6; ++r) {
+        // the row in registers: every index into pr is a compile-time constant
+        // (the loops run to kMaxNv under conditions uniform across the wave)
         c128 pr[kMaxNv];
+#pragma unroll
+        for (int k = 0; k < kMaxNv; ++k) pr[k] = c128{0, 0};
         for (int jj = 0; jj < Nv; ++jj) {
           c128 v = field(jj)[(long long)(6 * h + r) * g.V + s];
-          for (int i = 0; i < jj; ++i) v = v - pr[i] * conj(L[jj][i]);
-          pr[jj] = (1.0 / L[jj][jj].re) * v;
+#pragma unroll
+          for (int i = 0; i < kMaxNv; ++i)
+            if (i < jj) v = v - pr[i] * conj(L[jj][i]);
+          const c128 pj = (1.0 / L[jj][jj].re) * v;
+#pragma unroll
+          for (int k = 0; k < kMaxNv; ++k)
+            if (k == jj) pr[k] = pj;
         }
-        for (int jj = 0; jj < Nv; ++jj) P[((long long)jj * 12 + 6 * h + r) * g.V + s] = pr[jj];
+#pragma unroll
+        for (int k = 0; k < kMaxNv; ++k)
+          if (k < Nv) P[((long long)k * 12 + 6 * h + r) * g.V + s] = pr[k];
       }
     }
     __syncthreads();
