@@ -2,7 +2,8 @@
 what fixes them independently: the Wilson-Dirac operator (one layer with the
 hopping weights is D), gauge covariance and translation equivariance (which a
 wrong path order, a missing dagger or a misplaced boundary sign breaks), the
-projector's two extreme cases, and finite differences for the gradients."""
+projector's two extreme cases, finite differences for the gradients, and the
+nonlinearity's radial-shift properties."""
 import numpy as np
 import pytest
 import torch
@@ -140,3 +141,44 @@ def test_loss_gradients_match_finite_differences():
         Lm = loss([p - h * d for p, d in zip(params, dirs)]).item()
     fd = (Lp - Lm) / (2 * h)
     assert abs(fd - dl) <= 1e-6 * max(abs(dl), 1e-3)
+
+
+def test_mod_relu_is_a_radial_shift_with_a_cut():
+    # Properties that fix the nonlinearity without restating it: per channel
+    # and site it keeps the direction of the spinor (a non-negative real
+    # factor), b = 0 is the identity, two shifts that cut nothing compose to
+    # their sum, scaling the field and the bias together scales the output,
+    # and a bias below minus the largest norm cuts every site to zero.  A norm
+    # squared in place of the norm, a wrong division or a flipped sign of b
+    # breaks one of them.
+    g = torch.Generator().manual_seed(141)
+    C, V = 3, 40
+    phi = torch.complex(torch.randn((C, 4, 3, V), generator=g, dtype=torch.float64),
+                        torch.randn((C, 4, 3, V), generator=g, dtype=torch.float64))
+    nrm = torch.sqrt((phi.abs() ** 2).sum(dim=(1, 2)))                        # [C, V]
+    rmin = float(nrm.min())
+    b1 = -0.3 * rmin * torch.rand(C, generator=g, dtype=torch.float64)
+    b2 = -0.3 * rmin * torch.rand(C, generator=g, dtype=torch.float64)
+    out = lcnn.mod_relu(phi, b1)
+    # direction kept: out = s phi with s real and >= 0
+    s = (phi.conj() * out).sum(dim=(1, 2)) / nrm ** 2
+    assert float(s.imag.abs().max()) < 1e-14 and float(s.real.min()) >= 0
+    assert float((out - s[:, None, None, :] * phi).abs().max()) < 1e-13
+    # the identity at b = 0
+    assert float((lcnn.mod_relu(phi, torch.zeros(C, dtype=torch.float64)) - phi).abs().max()) < 1e-14
+    # shifts that cut nothing compose
+    two = lcnn.mod_relu(lcnn.mod_relu(phi, b1), b2)
+    assert float((two - lcnn.mod_relu(phi, b1 + b2)).abs().max()) < 1e-13
+    # joint scaling
+    alpha = 2.7
+    assert float((lcnn.mod_relu(alpha * phi, alpha * b1) - alpha * out).abs().max()) < 1e-13
+    # the cut
+    cut = lcnn.mod_relu(phi, -1.01 * float(nrm.max()) * torch.ones(C, dtype=torch.float64))
+    assert float(cut.abs().max()) == 0.0
+    # a partial cut: exactly the sites with |phi| below -b vanish, the others keep |phi| + b
+    bm = -float(nrm.median()) * torch.ones(C, dtype=torch.float64)
+    part = lcnn.mod_relu(phi, bm)
+    pn = torch.sqrt((part.abs() ** 2).sum(dim=(1, 2)))
+    kept = nrm > -bm[:, None]
+    assert bool(torch.all(pn[~kept] == 0))
+    assert float((pn[kept] - (nrm + bm[:, None])[kept]).abs().max()) < 1e-13
