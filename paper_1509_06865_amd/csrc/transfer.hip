@@ -221,21 +221,26 @@ __global__ void __launch_bounds__(256) k_build_P(Geom g, const c128 *const *__re
       L[jj][i] = c128{re, -im};       // G[j][i] = conj(G[i][j]), lower triangle
     }
     __syncthreads();
-    if (t == 0) {
-      // G = L L^dag:  L[i][j] = (G[i][j] - sum_{k<j} L[i][k] conj(L[j][k])) / L[j][j]
-      for (int jj = 0; jj < Nv; ++jj) {
+    // G = L L^dag:  L[i][j] = (G[i][j] - sum_{k<j} L[i][k] conj(L[j][k])) / L[j][j], column by
+    // column: the pivot by thread 0, then the rows below it, one thread each (every entry
+    // accumulates over k in the same order as a serial loop would)
+    for (int jj = 0; jj < Nv; ++jj) {
+      if (t == 0) {
         const double gjj = L[jj][jj].re;
         double d = gjj;
         for (int k = 0; k < jj; ++k) d -= norm2(L[jj][k]);
-        if (!(d > 1e-13 * gjj) || !(gjj > 0)) { bad = 1; break; }
-        const double ljj = sqrt(d);
-        L[jj][jj] = c128{ljj, 0};
-        for (int i = jj + 1; i < Nv; ++i) {
-          c128 v = L[i][jj];
-          for (int k = 0; k < jj; ++k) v = v - cmul_conj(L[jj][k], L[i][k]);
-          L[i][jj] = (1.0 / ljj) * v;
-        }
+        if (!(d > 1e-13 * gjj) || !(gjj > 0)) bad = 1;
+        else L[jj][jj] = c128{sqrt(d), 0};
       }
+      __syncthreads();
+      if (bad) break;                  // the same for the whole workgroup
+      const double ljj = L[jj][jj].re;
+      for (int i = jj + 1 + t; i < Nv; i += blockDim.x) {
+        c128 v = L[i][jj];
+        for (int k = 0; k < jj; ++k) v = v - cmul_conj(L[jj][k], L[i][k]);
+        L[i][jj] = (1.0 / ljj) * v;
+      }
+      __syncthreads();
     }
     __syncthreads();
     if (bad) break;                    // the same for the whole workgroup: keep the old block
